@@ -1,0 +1,506 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper or by mathematics.
+
+None of these tests re-types the oracle's matrix or right-hand side.  They
+compare it against
+  * numpy's Gauss-Legendre rule and linear solver,
+  * the corner-balance equations written as residuals (tests/balance.py),
+    solved globally with numpy,
+  * the Fourier symbols of the OCI and SI splittings built from those
+    residuals (the paper's Fourier analysis of the iteration),
+  * closed forms of the flat infinite-medium time step,
+  * exact finite termination of the pure absorber,
+  * global particle balance,
+  * second-order convergence on manufactured solutions (the paper's claim
+    of a second-order space-time scheme),
+  * the steady-state row of the paper's Table 1 (golden fixture).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import balance as B
+import oracle
+from paper_2503_00264_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny_mg(seed=7, J=6, N=4, G=2, dt=0.2):
+    p = W.multigroup(seed=seed, J=J, N=N, G=G, n_regions=2 if J % 2 == 0 else 1, length=1.0,
+                     speeds=(3.0, 1.0, 0.5, 0.25)[:G], dt=dt, steps=1, source_regions=1)
+    return p
+
+
+def nonzero_bc(p, seed=11):
+    rng = np.random.default_rng(seed)
+    h = p["N"] // 2
+    inc_l = rng.uniform(0.0, 1.0, size=(2, p["G"], h))
+    inc_r = rng.uniform(0.0, 1.0, size=(2, p["G"], h))
+    psi_prev = rng.uniform(0.0, 1.0, size=(p["J"], p["G"], p["N"], 2))
+    return inc_l, inc_r, psi_prev
+
+
+# ------------------------------------------------------------------ basics
+def _gl_reference(N):
+    """Gauss-Legendre nodes and weights in 40-digit arithmetic (mpmath)."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    xs, ws = [], []
+    for i in range(N):
+        x = mp.cos(mp.pi * (i + mp.mpf(3) / 4) / (N + mp.mpf(1) / 2))
+        for _ in range(60):
+            d = N * (x * mp.legendre(N, x) - mp.legendre(N - 1, x)) / (x * x - 1)
+            x = x - mp.legendre(N, x) / d
+        d = N * (x * mp.legendre(N, x) - mp.legendre(N - 1, x)) / (x * x - 1)
+        xs.append(float(x))
+        ws.append(float(2 / ((1 - x * x) * d * d)))
+    return np.array(xs[::-1]), np.array(ws[::-1])
+
+
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 32, 64])
+def test_gauss_legendre_matches_high_precision(N):
+    mu, w = oracle.gauss_legendre(N)
+    mr, wr = _gl_reference(N)
+    assert np.max(np.abs(mu - mr)) < 4e-16
+    assert np.max(np.abs(w - wr) / wr) < 2e-13
+    assert abs(w.sum() - 2.0) < 1e-14
+    # exact for polynomials of degree 2N - 1; symmetric about 0
+    for k in (2, N, 2 * N - 2):
+        assert abs(np.sum(w * mu ** k) - 2.0 / (k + 1)) < 1e-14
+    assert np.all(np.diff(mu) > 0)
+    assert np.max(np.abs(mu + mu[::-1])) < 4e-16
+    # and numpy's (less accurate near the ends) rule agrees to its own accuracy
+    mn, wn = np.polynomial.legendre.leggauss(N)
+    assert np.max(np.abs(mu - mn)) < 1e-14 and np.max(np.abs(w - wn) / wn) < 1e-11
+
+
+def test_gauss_legendre_rejects_odd():
+    mu = np.empty(3)
+    w = np.empty(3)
+    assert oracle.lib().orc_gauss_legendre(3, mu.ctypes.data, w.ctypes.data) == oracle.ERR_INVALID
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 7, 32, 64])
+def test_lu_solve_matches_numpy(n):
+    rng = np.random.default_rng(n)
+    A = rng.normal(size=(n, n))
+    b = rng.normal(size=n)
+    LU, piv, rc = oracle.lu_factor(A)
+    assert rc == 0
+    x = oracle.lu_solve(LU, piv, b)
+    xr = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) < 1e-12
+
+
+def test_lu_factor_reconstructs_with_pivoting():
+    # zero leading entry forces an exchange; P A = L U must hold
+    rng = np.random.default_rng(3)
+    A = rng.normal(size=(9, 9))
+    A[0, 0] = 0.0
+    LU, piv, rc = oracle.lu_factor(A)
+    assert rc == 0
+    L = np.tril(LU, -1) + np.eye(9)
+    U = np.triu(LU)
+    PA = A.copy()
+    for k, p in enumerate(piv):
+        PA[[k, p]] = PA[[p, k]]
+    assert np.max(np.abs(PA - L @ U)) < 1e-13
+    assert np.all(np.abs(np.tril(LU, -1)) <= 1.0 + 1e-15)   # partial pivoting bound
+
+
+def test_lu_pivot_ties_take_lowest_row():
+    A = np.array([[1.0, 2.0, 0.0], [-3.0, 1.0, 1.0], [3.0, 0.0, 2.0]])
+    _, piv, rc = oracle.lu_factor(A)
+    assert rc == 0 and piv[0] == 1
+
+
+def test_lu_singular_reported():
+    A = np.ones((4, 4))
+    _, _, rc = oracle.lu_factor(A)
+    assert rc == oracle.ERR_SINGULAR
+
+
+# ------------------------------------------- fixed points vs the balances
+def test_oci_fixed_point_is_the_discrete_solution():
+    p = tiny_mg()
+    inc_l, inc_r, psi_prev = nonzero_bc(p)
+    o = oracle.Oracle(p)
+    pp, pi = o.initial_state(psi_prev)
+    _, info = o.step("oci", pp, pi, q=p["q"], inc_l=inc_l, inc_r=inc_r, tol=1e-15,
+                     max_iters=20000)
+    assert info["status"] == 0
+    x = B.direct_solve(p, psi_prev, q=p["q"], inc_l=inc_l, inc_r=inc_r)
+    assert np.max(np.abs(pi - x)) / np.max(np.abs(x)) < 1e-12
+    # and the balance residuals of the oracle's answer vanish
+    r = B.residual(p, pi, psi_prev, q=p["q"], inc_l=inc_l, inc_r=inc_r)
+    assert np.max(np.abs(r)) < 1e-12
+    # the time update hands psi_{k+1/2} on
+    assert np.array_equal(pp, pi[..., 2:4])
+
+
+def test_si_fixed_point_is_the_discrete_solution():
+    p = tiny_mg()
+    inc_l, inc_r, psi_prev = nonzero_bc(p)
+    o = oracle.Oracle(p)
+    pp, pi = o.initial_state(psi_prev)
+    _, info = o.step("si", pp, pi, q=p["q"], inc_l=inc_l, inc_r=inc_r, tol=1e-15,
+                     max_iters=20000)
+    assert info["status"] == 0
+    x = B.direct_solve(p, psi_prev, q=p["q"], inc_l=inc_l, inc_r=inc_r)
+    assert np.max(np.abs(pi - x)) / np.max(np.abs(x)) < 1e-12
+
+
+def test_oci_and_si_agree_over_steps():
+    p = W.regions(seed=2, J=128, N=8, n_regions=8, length=4.0, dt=0.05, steps=4)
+    o = oracle.Oracle(p)
+    a = o.run("oci", tol=1e-14)
+    b = o.run("si", tol=1e-14)
+    ref = np.max(np.abs(a["phi"]))
+    assert np.max(np.abs(a["phi"] - b["phi"])) / ref < 1e-12
+
+
+def test_per_angle_source_equals_isotropic_when_isotropic():
+    p = tiny_mg()
+    o = oracle.Oracle(p)
+    q_ang = np.repeat(0.5 * p["q"][:, :, None, :], p["N"], axis=2)
+    pp1, pi1 = o.initial_state()
+    pp2, pi2 = o.initial_state()
+    o.step("oci", pp1, pi1, q=p["q"], fixed_iters=5)
+    o.step("oci", pp2, pi2, q_ang=q_ang, fixed_iters=5)
+    assert np.max(np.abs(pi1 - pi2)) < 1e-15
+
+
+# ------------------------------------------------ exact finite termination
+def test_pure_absorber_oci_terminates_within_J_plus_1():
+    # no scattering: information crosses one cell per iteration, so the
+    # Jacobi iteration is nilpotent and stops changing after J iterations
+    p = W.homogeneous(J=10, N=4, c=0.0, dt=0.3, steps=1)
+    o = oracle.Oracle(p)
+    pp, pi = o.initial_state()
+    _, info = o.step("oci", pp, pi, q=p["q"], tol=0.0, max_iters=100, history=True)
+    assert info["status"] == 0
+    assert info["iterations"] <= p["J"] + 1
+    assert info["e_hist"][-1] == 0.0
+    x = B.direct_solve(p, np.zeros((10, 1, 4, 2)), q=p["q"])
+    assert np.max(np.abs(pi - x)) / np.max(np.abs(x)) < 1e-13
+
+
+def test_pure_absorber_si_exact_after_one_sweep():
+    p = W.homogeneous(J=10, N=4, c=0.0, dt=0.3, steps=1)
+    o = oracle.Oracle(p)
+    pp, pi = o.initial_state()
+    _, info = o.step("si", pp, pi, q=p["q"], tol=0.0, max_iters=100, history=True)
+    assert info["iterations"] == 2 and info["e_hist"][1] == 0.0
+
+
+def test_single_cell_converges_in_one_solve():
+    p = tiny_mg(J=1)
+    inc_l, inc_r, psi_prev = nonzero_bc(p)
+    o = oracle.Oracle(p)
+    pp, pi = o.initial_state(psi_prev)
+    _, info = o.step("oci", pp, pi, q=p["q"], inc_l=inc_l, inc_r=inc_r, tol=1e-10,
+                     history=True)
+    assert info["iterations"] == 2 and info["e_hist"][1] == 0.0
+    x = B.direct_solve(p, psi_prev, q=p["q"], inc_l=inc_l, inc_r=inc_r)
+    assert np.max(np.abs(pi - x)) / np.max(np.abs(x)) < 1e-13
+
+
+# ------------------------------------------- flat infinite medium (closed form)
+def flat_closed_form(sig_t, ss, v, dt, q, phi_prev):
+    """Scalar flux of one MB step in an infinite homogeneous medium.
+
+    Summing the two time balances over angles with a flat, isotropic flux:
+      a (phi_h - phi_prev) + R phi_k = Q,  2a (phi_h - phi_k) + R phi_h = Q,
+    a = diag(1/(v dt)), R = diag(sigma_t) - Ss (removal); solved as 2G x 2G.
+    """
+    G = len(sig_t)
+    a = np.diag(1.0 / (v * dt))
+    R = np.diag(sig_t) - ss
+    M = np.block([[R, a], [-2 * a, 2 * a + R]])
+    rhs = np.concatenate([q + a @ phi_prev, q])
+    sol = np.linalg.solve(M, rhs)
+    return sol[:G], sol[G:]
+
+
+@pytest.mark.parametrize("G", [1, 3])
+@pytest.mark.parametrize("method", ["oci", "si"])
+def test_infinite_medium_time_steps(G, method):
+    rng = np.random.default_rng(5)
+    J, N, dt = 4, 6, 0.37
+    st = rng.uniform(0.5, 2.0, size=G)
+    ss = rng.uniform(0.0, 0.3, size=(G, G)) * st[None, :]
+    v = rng.uniform(0.5, 3.0, size=G)
+    qg = rng.uniform(0.5, 1.5, size=G)
+    p = dict(J=J, N=N, G=G, dx=np.full(J, 0.7), sigma_t=np.tile(st, (J, 1)),
+             sigma_s=np.tile(ss, (J, 1, 1)), speed=v, dt=dt)
+    q = np.tile(qg[None, :, None], (J, 1, 4))
+    o = oracle.Oracle(p, periodic=True)
+    phi0 = rng.uniform(0.5, 1.0, size=G)
+    psi_init = np.tile((0.5 * phi0)[None, :, None, None], (J, 1, N, 2))
+    pp, pi = o.initial_state(psi_init)
+    phi_prev = phi0
+    for _ in range(5):
+        phi, info = o.step(method, pp, pi, q=q, tol=1e-15, max_iters=5000)
+        pk, ph = flat_closed_form(st, ss, v, dt, qg, phi_prev)
+        assert np.max(np.abs(phi[:, :, 0] - pk[None, :])) < 1e-13 * max(1, np.abs(pk).max())
+        assert np.max(np.abs(phi[:, :, 1] - pk[None, :])) < 1e-13 * max(1, np.abs(pk).max())
+        assert np.max(np.abs(phi[:, :, 2] - ph[None, :])) < 1e-13 * max(1, np.abs(ph).max())
+        assert np.max(np.abs(phi[:, :, 3] - ph[None, :])) < 1e-13 * max(1, np.abs(ph).max())
+        phi_prev = ph
+
+
+def test_time_decay_factor_without_source():
+    # Q = 0, one group: phi_{k+1/2} / phi_{k-1/2} = 2 / (2 + 2 tau_a + tau_a^2)
+    J, N, dt, v, st, c = 3, 4, 0.8, 1.7, 1.3, 0.4
+    p = dict(J=J, N=N, G=1, dx=np.full(J, 0.5), sigma_t=np.full((J, 1), st),
+             sigma_s=np.full((J, 1, 1), c * st), speed=np.array([v]), dt=dt)
+    o = oracle.Oracle(p, periodic=True)
+    pp, pi = o.initial_state(np.full((J, 1, N, 2), 0.5))
+    phi, _ = o.step("oci", pp, pi, q=np.zeros((J, 1, 4)), tol=1e-15)
+    tau_a = (1 - c) * st * v * dt
+    assert abs(phi[0, 0, 2] - 2.0 / (2 + 2 * tau_a + tau_a ** 2)) < 1e-14
+
+
+# -------------------------------------------------- Fourier spectrum pins
+def _oracle_oci_operator(o, p):
+    J, N, G = p["J"], p["N"], p["G"]
+    nu = J * G * N * 4
+    zp = np.zeros((J, G, N, 2))
+    T = np.zeros((nu, nu))
+    for i in range(nu):
+        e = np.zeros(nu)
+        e[i] = 1.0
+        T[:, i] = o.oci_iterate(e.reshape(J, G, N, 4), zp).reshape(nu)
+    return T
+
+
+def _match(ev, sym, tol):
+    big = sym[np.abs(sym) > 1e-8]
+    return max(np.min(np.abs(ev - s)) for s in big) < tol
+
+
+@pytest.mark.parametrize("G,dx,dt,c", [(1, 0.3, 0.5, 0.9), (1, 0.05, 2.0, 0.99),
+                                         (2, 0.2, 0.3, None)])
+def test_oci_spectrum_matches_fourier_symbol(G, dx, dt, c):
+    J, N = 8, 4
+    if G == 1:
+        p = W.homogeneous(J=J, N=N, length=J * dx, c=c, dt=dt)
+    else:
+        p = W.multigroup(seed=9, J=J, N=N, G=G, n_regions=1, length=J * dx,
+                         speeds=(2.0, 1.0), dt=dt)
+    o = oracle.Oracle(p, periodic=True, methods=("oci",))
+    ev = np.linalg.eigvals(_oracle_oci_operator(o, p))
+    p1 = B.one_cell(p)
+    sym = np.concatenate([np.linalg.eigvals(B.oci_symbol(p1, 2 * np.pi * k / J))
+                          for k in range(J)])
+    assert abs(np.abs(ev).max() - np.abs(sym).max()) < 1e-12
+    assert _match(ev, sym, 1e-9)
+
+
+@pytest.mark.parametrize("c,tau", [(0.9, 0.5), (0.5, 3.0), (0.999, 0.1)])
+def test_si_spectrum_matches_fourier_symbol(c, tau):
+    J, N = 8, 4
+    p = W.homogeneous(J=J, N=N, length=J * 0.3, c=c, dt=tau)   # sigma = v = 1
+    o = oracle.Oracle(p, periodic=True, methods=("si",))
+    mu, w = np.polynomial.legendre.leggauss(N)
+    nphi = J * 4
+    zp = np.zeros((J, 1, N, 2))
+    T = np.zeros((nphi, nphi))
+    for i in range(nphi):
+        e = np.zeros(nphi)
+        e[i] = 1.0
+        ps = o.si_sweep(e.reshape(J, 1, 4), zp)
+        T[:, i] = np.einsum("n,jgnu->jgu", w, ps).reshape(nphi)
+    ev = np.linalg.eigvals(T)
+    p1 = B.one_cell(p)
+    sym = np.concatenate([np.linalg.eigvals(B.si_symbol(p1, 2 * np.pi * k / J))
+                          for k in range(J)])
+    assert abs(np.abs(ev).max() - np.abs(sym).max()) < 1e-12
+    assert _match(ev, sym, 1e-9)
+    # flat-mode closed form of the SI rate in an infinite medium
+    flat = c / np.sqrt((1 + 1 / tau) ** 2 + (1 / tau) ** 2)
+    assert abs(np.abs(ev).max() - flat) < 1e-12
+
+
+def test_steady_state_oci_radius_is_one_at_c1():
+    g = json.load(open(os.path.join(GOLDEN, "table1_steady_state.json")))
+    for delta, rho in zip(g["delta"], g["rho"]):
+        J = 8
+        p = W.homogeneous(J=J, N=g["quadrature_order"], length=J * delta,
+                          c=g["scattering_ratio"], dt=1e13)
+        o = oracle.Oracle(p, periodic=True, methods=("oci",))
+        ev = np.linalg.eigvals(_oracle_oci_operator(o, p))
+        assert abs(np.abs(ev).max() - rho) < 0.5 * 10 ** -g["printed_digits"]
+
+
+def test_transient_radius_trends():
+    # Results section: with time dependence rho < 1 at c = 1, and rho falls
+    # as the mean free time shrinks and as the cells thicken.
+    def rho(delta, tau):
+        p1 = dict(J=1, N=8, G=1, dx=np.array([delta]), sigma_t=np.array([[1.0]]),
+                  sigma_s=np.array([[[1.0]]]), speed=np.array([1.0]), dt=tau)
+        return max(np.abs(np.linalg.eigvals(B.oci_symbol(p1, t))).max()
+                   for t in np.linspace(0, 2 * np.pi, 65))
+    grid = [[rho(d, t) for d in (10.0, 1.0, 0.1)] for t in (10.0, 1.0, 0.1)]
+    grid = np.array(grid)
+    assert np.all(grid < 1.0)
+    assert np.all(np.diff(grid, axis=0) < 0)     # smaller tau -> smaller rho
+    assert np.all(np.diff(grid, axis=1) > 0)     # thinner cells -> larger rho
+
+
+# ------------------------------------------------------ particle balance
+@pytest.mark.parametrize("method", ["oci", "si"])
+def test_particle_balance(method):
+    p = W.multigroup(seed=13, J=24, N=6, G=3, n_regions=4, length=3.0,
+                     speeds=(5.0, 1.0, 0.2), dt=0.4, steps=2)
+    o = oracle.Oracle(p)
+    mu, w = np.polynomial.legendre.leggauss(p["N"])
+    pp, pi = o.initial_state()
+    for _ in range(2):
+        prev = pp.copy()
+        phi, _ = o.step(method, pp, pi, q=p["q"], tol=1e-15, max_iters=50000)
+        phi_prev = np.einsum("n,jgnc->jgc", w, prev)
+        dx = p["dx"][:, None]
+        v = p["speed"][None, :]
+        h = p["N"] // 2
+        for lev in (0, 1):
+            cL, cR = (0, 1) if lev == 0 else (2, 3)
+            ph = phi[:, :, cL] + phi[:, :, cR]
+            scat = np.einsum("jgh,jh->jg", p["sigma_s"], ph)
+            src = p["q"][:, :, cL] + p["q"][:, :, cR]
+            if lev == 0:
+                dphi = (phi[:, :, 2] + phi[:, :, 3]) - (phi_prev[:, :, 0] + phi_prev[:, :, 1])
+                timet = dphi / (v * p["dt"])
+            else:
+                dphi = (phi[:, :, 2] + phi[:, :, 3]) - (phi[:, :, 0] + phi[:, :, 1])
+                timet = 2 * dphi / (v * p["dt"])
+            vol = np.sum(dx / 2 * (timet + p["sigma_t"] * ph - scat - src), axis=0)
+            out_r = np.einsum("m,gm->g", (w * mu)[h:], pi[-1, :, h:, cR])
+            out_l = np.einsum("m,gm->g", (w * mu)[:h], pi[0, :, :h, cL])
+            total = vol + out_r - out_l
+            scale = np.sum(dx / 2 * src, axis=0)
+            assert np.max(np.abs(total) / scale) < 1e-12
+
+
+# ----------------------------------------------- manufactured solutions
+_gx, _gw = np.polynomial.legendre.leggauss(12)
+
+
+def _avg(fun, a, b):
+    """Average of fun over [a, b] (arrays of intervals), 12-point Gauss rule."""
+    xs = 0.5 * (b - a)[..., None] * _gx + 0.5 * (a + b)[..., None]
+    return 0.5 * np.sum(_gw * fun(xs), axis=-1)
+
+
+def test_scb_space_order_two():
+    # steady (dt -> infinity) manufactured psi = f(mu) X(x): the corner
+    # balances converge at second order in the cell averages
+    N, sig, c, L = 4, 1.0, 0.5, 1.0
+    mu, w = np.polynomial.legendre.leggauss(N)
+    f = 1.0 + 0.5 * mu + mu * mu
+    F = np.sum(w * f)
+    X = lambda x: 1.0 + 0.5 * np.sin(np.pi * x / L)
+    Xp = lambda x: 0.5 * np.pi / L * np.cos(np.pi * x / L)
+    errs = []
+    for J in (16, 32, 64):
+        e = np.arange(J + 1) * (L / J)
+        xm = 0.5 * (e[:-1] + e[1:])
+        p = dict(J=J, N=N, G=1, dx=np.full(J, L / J), sigma_t=np.full((J, 1), sig),
+                 sigma_s=np.full((J, 1, 1), c * sig), speed=np.array([1.0]), dt=1e12)
+        o = oracle.Oracle(p, methods=("oci",))
+        qa = np.zeros((J, 1, N, 4))
+        for m in range(N):
+            qf = lambda x: f[m] * sig * X(x) + mu[m] * f[m] * Xp(x) - 0.5 * sig * c * F * X(x)
+            qa[:, 0, m, 0] = qa[:, 0, m, 2] = _avg(qf, e[:-1], xm)
+            qa[:, 0, m, 1] = qa[:, 0, m, 3] = _avg(qf, xm, e[1:])
+        h = N // 2
+        inc_l = np.zeros((2, 1, h))
+        inc_r = np.zeros((2, 1, h))
+        inc_l[:, 0, :] = f[h:] * X(0.0)
+        inc_r[:, 0, :] = f[:h] * X(L)
+        pp, pi = o.initial_state()
+        o.step("oci", pp, pi, q_ang=qa, inc_l=inc_l, inc_r=inc_r, tol=1e-14, max_iters=10 ** 6)
+        cell = 0.5 * (pi[:, 0, :, 0] + pi[:, 0, :, 1])
+        exact = f[None, :] * _avg(X, e[:-1], e[1:])[:, None]
+        errs.append(np.max(np.abs(cell - exact)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] > 1.9, orders
+
+
+def test_mb_time_order_two():
+    # flat manufactured psi = f(mu) T(t) on a periodic mesh: the multiple
+    # balance step converges at second order in time
+    N, sig, c, v = 4, 1.0, 0.5, 1.0
+    mu, w = np.polynomial.legendre.leggauss(N)
+    f = 1.0 + 0.5 * mu + mu * mu
+    F = np.sum(w * f)
+    T = lambda t: np.exp(-t) + 0.5 * np.sin(2 * t)
+    Tp = lambda t: -np.exp(-t) + np.cos(2 * t)
+    errs = []
+    for steps in (8, 16, 32):
+        dt = 1.0 / steps
+        J = 2
+        p = dict(J=J, N=N, G=1, dx=np.full(J, 0.5), sigma_t=np.full((J, 1), sig),
+                 sigma_s=np.full((J, 1, 1), c * sig), speed=np.array([v]), dt=dt)
+        o = oracle.Oracle(p, periodic=True, methods=("oci",))
+        pp, pi = o.initial_state(np.tile((f * T(0.0))[None, None, :, None], (J, 1, 1, 2)))
+        for k in range(steps):
+            t0, t1 = k * dt, (k + 1) * dt
+            qa = np.zeros((J, 1, N, 4))
+            for m in range(N):
+                qf = lambda t: f[m] * (Tp(t) / v + sig * T(t)) - 0.5 * sig * c * F * T(t)
+                qa[:, 0, m, 0:2] = _avg(qf, np.array(t0), np.array(t1))
+                qa[:, 0, m, 2:4] = qf(t1)
+            o.step("oci", pp, pi, q_ang=qa, tol=1e-14, max_iters=10 ** 6)
+        errs.append(np.max(np.abs(pp - (f * T(1.0))[None, None, :, None])))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] > 1.95, orders
+
+
+# ------------------------------------------------------- stopping rule
+def test_stop_rule_cap_and_fixed_count():
+    p = W.homogeneous(J=16, N=4)
+    o = oracle.Oracle(p)
+    pp, pi = o.initial_state()
+    _, info = o.step("oci", pp, pi, q=p["q"], tol=1e-10, max_iters=1)
+    assert info["status"] == oracle.NOT_CONVERGED and info["iterations"] == 1
+    pp, pi = o.initial_state()
+    _, info = o.step("oci", pp, pi, q=p["q"], fixed_iters=7)
+    assert info["status"] == 0 and info["iterations"] == 7
+
+
+def test_stop_rule_nonfinite_source():
+    p = W.homogeneous(J=8, N=4)
+    o = oracle.Oracle(p)
+    q = p["q"].copy()
+    q[3, 0, 1] = np.nan
+    pp, pi = o.initial_state()
+    _, info = o.step("oci", pp, pi, q=q, tol=1e-10)
+    assert info["status"] == oracle.NONFINITE
+
+
+def test_stop_rule_matches_definition():
+    # the reported stop satisfies e_l < eps (1 - e_l / e_{l-1}) and no
+    # earlier iteration did
+    p = W.regions(seed=2, J=64, N=8, n_regions=8, length=4.0, dt=0.1, steps=1)
+    o = oracle.Oracle(p)
+    for norm in (oracle.NORM_SCALAR, oracle.NORM_ANGULAR):
+        pp, pi = o.initial_state()
+        _, info = o.step("oci", pp, pi, q=p["q"], tol=1e-8, history=True, norm=norm)
+        e = info["e_hist"]
+        ok = [l >= 1 and e[l] < 1e-8 * (1 - e[l] / e[l - 1]) for l in range(len(e))]
+        assert ok[-1] and not any(ok[:-1])
+
+
+def test_workload_recipes_match_table2():
+    g = json.load(open(os.path.join(GOLDEN, "rosa_table2.json")))
+    p = W.rosa(J=10)
+    assert np.allclose(p["sigma_t"][0], g["sigma_t"])
+    assert np.allclose(np.diag(p["sigma_s"][0]), g["within_group"])
+    ratio = p["sigma_s"][0].sum(axis=0) / p["sigma_t"][0]
+    assert abs(ratio[0] - g["scattering_ratio_printed"][0]) < 1e-5
+    tau = p["sigma_t"][0, 1] * p["speed"][1] * np.array([10.0, 0.1])
+    assert abs(tau[0] - g["mean_free_time_printed"]["dt_10s"]) < 1e-4
+    assert abs(tau[1] - g["mean_free_time_printed"]["dt_0.1s"]) < 1e-4
