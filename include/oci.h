@@ -1,0 +1,180 @@
+/*
+ * oci.h -- C ABI of liboci, the MI355X (gfx950) one-cell-inversion library for
+ * slab-geometry, multigroup, time-dependent discrete-ordinates (S_N) transport
+ * with simple-corner-balance (SCB) space and multiple-balance (MB) time
+ * discretisation (arXiv 2503.00264).
+ *
+ * What is computed (paper section 2):
+ *   The unknowns of cell j are the angular fluxes psi_{g,m,u} for group g,
+ *   Gauss-Legendre angle m and component u = 0: (k,L), 1: (k,R),
+ *   2: (k+1/2,L), 3: (k+1/2,R) (eq. x_vec, group-major as in eqs.
+ *   fullOCIlhs/fullOCIrhs); n = 4 N G unknowns per cell.  They satisfy the four
+ *   corner balances (eqs. scb-mb-a..d) with the midpoint closure and the
+ *   upstream edge closure.
+ *   oci_step performs one time step with the one-cell-inversion iteration of
+ *   eq. (oci): every cell solves A_j Psi_j^(l+1) = b_j(Psi^(l)) with
+ *   A_j = blockdiag(L_c) - S (eqs. Aj, scatter, scatter_mg, fullOCIlhs) and
+ *   b_j from eq. (rhs_sg), the incident edge fluxes lagged (block Jacobi over
+ *   cells), until the stopping rule of section 2.1 holds.
+ *   si_step performs the same time step with source iteration (Appendix A:
+ *   eqs. si_sys, si_rhs, si_sf; Algorithm 1), all groups and angles swept in
+ *   parallel with the whole scattering source lagged (Jacobi in groups).
+ *
+ * Stopping rule (section 2.1; Algorithms 1 and 2): after iteration l >= 1,
+ *   stop when e_l < tol (1 - e_l / e_{l-1}), e_l = ||x^(l+1) - x^(l)||_2 over
+ *   every (cell, group, corner, time level) of the scalar flux
+ *   phi = sum_m w_m psi_m (OCI_NORM_SCALAR; SI always uses it) or of the
+ *   angular flux (OCI_NORM_ANGULAR, Algorithm 2).  e_l == 0 stops.  Reaching
+ *   max_iters stops with OCI_NOT_CONVERGED; a non-finite e_l stops with
+ *   OCI_NONFINITE.
+ *
+ * First iterate of a step: the last iterate of the previous step (all four
+ * components); after oci_setup or oci_set_state it is psi_prev copied to both
+ * time levels.  After a step the state psi_{k-1/2} <- psi_{k+1/2} (the time
+ * update).
+ *
+ * Precision:
+ *   OCI_FP64          cell systems factored (LU, partial pivoting) and applied
+ *                     in FP64.
+ *   OCI_FP32_REFINED  factored and applied in FP32; each iteration is the
+ *                     refinement step Psi^(l+1) = Psi^(l) + A^-1 (b - A Psi^(l))
+ *                     with the residual in FP64 (power-of-two scaled before the
+ *                     FP32 solve).  Its fixed point is the FP64 one; the norm
+ *                     and the time update stay FP64.
+ *
+ * Memory and streams:
+ *   Pointers named *_dev are device memory owned by the caller; host arrays are
+ *   read during the call only.  All arrays are C order, float64.  The library
+ *   allocates no device memory: everything it keeps (factors, iterates,
+ *   control blocks) lives in the caller's workspace, sized by
+ *   oci_workspace_bytes and aligned to 256 bytes.  All GPU work is enqueued on
+ *   the stream given to oci_setup (a hipStream_t passed as void *; NULL = the
+ *   null stream).  oci_setup synchronises that stream once (to report a
+ *   singular cell); oci_step and si_step may synchronise it to learn
+ *   convergence but never the device.  Step results land in *info_dev
+ *   asynchronously.  A handle is not thread-safe; one handle must not be used
+ *   from two streams at once.
+ *
+ * Errors: every call returns an oci_status; negative values are errors and
+ * leave the handle usable unless stated.  Arguments are validated on the host
+ * before anything is launched.
+ */
+#ifndef OCI_H
+#define OCI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OCI_OK = 0,
+    OCI_NOT_CONVERGED = 1,     /* max_iters reached (step result, in info) */
+    OCI_NONFINITE = 2,         /* e_l not finite (step result, in info) */
+    OCI_ERR_INVALID = -1,      /* bad argument; nothing was launched */
+    OCI_ERR_HIP = -2,          /* a HIP runtime call failed */
+    OCI_ERR_SINGULAR = -3,     /* a cell matrix has a zero pivot */
+    OCI_ERR_WORKSPACE = -4,    /* workspace NULL, too small or misaligned */
+    OCI_ERR_UNSUPPORTED = -5,  /* shape beyond the compiled kernels (4NG > 512) */
+    OCI_ERR_DEVICE = -6        /* a device-side guard tripped (barrier spin limit) */
+} oci_status;
+
+typedef enum { OCI_FP64 = 0, OCI_FP32_REFINED = 1 } oci_precision;
+typedef enum { OCI_NORM_SCALAR = 0, OCI_NORM_ANGULAR = 1 } oci_norm;
+
+/* Problem description.  Host pointers, read during oci_setup only. */
+typedef struct {
+    int32_t J;                /* cells, >= 1 */
+    int32_t N;                /* Gauss-Legendre angles, even, >= 2 */
+    int32_t G;                /* energy groups, >= 1; 4 N G <= 512 */
+    const double *dx;         /* [J] cell widths (cm), > 0 */
+    const double *sigma_t;    /* [J][G] total cross sections (1/cm), >= 0 */
+    const double *sigma_s;    /* [J][G][G], [j][g][gp] = scattering gp -> g, >= 0 */
+    const double *speed;      /* [G] particle speeds (cm/s), > 0 */
+    double dt;                /* time-step size (s), > 0 */
+    double tol;               /* epsilon of the stopping rule, >= 0 */
+    int32_t max_iters;        /* >= 1 */
+    int32_t fixed_iters;      /* > 0: run exactly this many iterations per step
+                                 with no stopping test (lock-step comparisons) */
+    int32_t precision;        /* oci_precision */
+    int32_t norm;             /* oci_norm, OCI only */
+} oci_desc;
+
+/* Per-step result, written to device memory by oci_step / si_step. */
+typedef struct {
+    int32_t iterations;       /* iterations performed in the step */
+    int32_t status;           /* OCI_OK, OCI_NOT_CONVERGED or OCI_NONFINITE */
+    double e_last;            /* e_l of the last iteration */
+    double rho_e;             /* e_l / e_{l-1} of the last iteration (NaN if l = 0) */
+} oci_step_info;
+
+typedef struct oci_handle oci_handle;
+
+/* Bytes of device workspace oci_setup needs for this description (OCI and SI
+ * together).  Returns OCI_ERR_INVALID / OCI_ERR_UNSUPPORTED for a bad one. */
+int oci_workspace_bytes(const oci_desc *desc, size_t *bytes);
+
+/* Validate, build the quadrature, upload the material data into the
+ * workspace, then assemble every cell matrix A_j (eqs. Aj, scatter_mg,
+ * fullOCIlhs) on the device and factor it (LU with partial pivoting, the
+ * paper's gesv factorisation) in the requested precision; the factors are
+ * kept, as the inverse they define, for every iteration of every step.  Also
+ * prepares the 4x4 SI cell systems.  State psi_prev = 0.  Synchronises the
+ * stream.  On success *out receives a handle (host memory, owned by the
+ * caller until oci_destroy). */
+int oci_setup(const oci_desc *desc, void *workspace_dev, size_t workspace_bytes,
+              void *stream, oci_handle **out);
+
+/* Replace the state psi_{k-1/2}: psi_prev_dev [J][G][N][2] (L, R corners),
+ * NULL = zero.  The first iterate of the next step becomes psi_prev copied to
+ * both time levels.  Asynchronous device-to-device copy. */
+int oci_set_state(oci_handle *h, const double *psi_prev_dev);
+
+/* Copy the state psi_{k-1/2} into psi_prev_dev [J][G][N][2]. Asynchronous. */
+int oci_get_state(const oci_handle *h, double *psi_prev_dev);
+
+/* One OCI time step (Algorithm 2; eq. oci).
+ *   q_dev         [J][G][4] isotropic source Q at (k,L), (k,R), (k+1/2,L),
+ *                 (k+1/2,R); NULL = no source
+ *   inc_left_dev  [2][G][N/2] incident flux at x = 0 for the mu > 0 angles in
+ *                 ascending order, time level k then k+1/2; NULL = vacuum
+ *   inc_right_dev [2][G][N/2] the same at x = X for the mu < 0 angles
+ *   phi_out_dev   [J][G][4] scalar flux of the last iterate (required)
+ *   psi_out_dev   [J][G][N][4] angular flux of the last iterate, NULL = skip
+ *   info_dev      one oci_step_info in device memory (required)
+ * The inputs must stay valid until the stream reaches the end of the step. */
+int oci_step(oci_handle *h, const double *q_dev, const double *inc_left_dev,
+             const double *inc_right_dev, double *phi_out_dev, double *psi_out_dev,
+             oci_step_info *info_dev);
+
+/* One source-iteration time step (Appendix A, Algorithm 1) on the same state
+ * and with the same arguments as oci_step. */
+int si_step(oci_handle *h, const double *q_dev, const double *inc_left_dev,
+            const double *inc_right_dev, double *phi_out_dev, double *psi_out_dev,
+            oci_step_info *info_dev);
+
+/* Instrumentation (not part of the method).  With on != 0, every later
+ * oci_step / si_step records a pair of HIP events on the handle's stream
+ * around its iteration kernels (OCI: the one persistent launch; SI: all sweep
+ * and flux launches of the step).  Event pairs are host-side objects owned by
+ * the handle; enabling costs two event records per step. */
+int oci_profile_enable(oci_handle *h, int on);
+
+/* Synchronise on the recorded events and return, since the last read (or
+ * the enable), the summed milliseconds of the iteration kernels in *ms and
+ * the number of steps recorded in *steps; then forget them. */
+int oci_profile_read(oci_handle *h, double *ms, int32_t *steps);
+
+/* Release the host-side handle.  The workspace stays the caller's. */
+int oci_destroy(oci_handle *h);
+
+/* Static text for a status code. */
+const char *oci_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCI_H */

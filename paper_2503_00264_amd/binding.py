@@ -1,0 +1,252 @@
+"""ctypes binding of liboci (include/oci.h): same names, argument marshalling only.
+
+Every computation happens in the gfx950 kernels of liboci.so.  This module
+loads the in-tree library (it raises if the library is missing or fails to
+load; there is no fallback), converts Python/torch arguments to plain pointers,
+and wraps status codes into exceptions.  `Solver` is a convenience holder of
+the device buffers one slab problem needs (workspace, inputs, outputs) on top
+of the same calls.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboci.so")
+
+OCI_OK, OCI_NOT_CONVERGED, OCI_NONFINITE = 0, 1, 2
+OCI_ERR_INVALID, OCI_ERR_HIP, OCI_ERR_SINGULAR = -1, -2, -3
+OCI_ERR_WORKSPACE, OCI_ERR_UNSUPPORTED, OCI_ERR_DEVICE = -4, -5, -6
+OCI_FP64, OCI_FP32_REFINED = 0, 1
+OCI_NORM_SCALAR, OCI_NORM_ANGULAR = 0, 1
+
+# every symbol include/oci.h declares
+EXPORTS = ("oci_workspace_bytes", "oci_setup", "oci_set_state", "oci_get_state",
+           "oci_step", "si_step", "oci_profile_enable", "oci_profile_read",
+           "oci_destroy", "oci_status_string")
+
+
+class OciError(RuntimeError):
+    def __init__(self, call, code):
+        self.code = code
+        super().__init__(f"{call} -> {code} ({oci_status_string(code)})")
+
+
+class oci_desc(C.Structure):
+    _fields_ = [("J", C.c_int32), ("N", C.c_int32), ("G", C.c_int32),
+                ("dx", C.c_void_p), ("sigma_t", C.c_void_p),
+                ("sigma_s", C.c_void_p), ("speed", C.c_void_p),
+                ("dt", C.c_double), ("tol", C.c_double),
+                ("max_iters", C.c_int32), ("fixed_iters", C.c_int32),
+                ("precision", C.c_int32), ("norm", C.c_int32)]
+
+
+class oci_step_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("status", C.c_int32),
+                ("e_last", C.c_double), ("rho_e", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded liboci.so; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2503_00264_amd.build` (no fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32 = C.c_void_p, C.c_int
+        D = C.POINTER(oci_desc)
+        L.oci_workspace_bytes.argtypes = [D, C.POINTER(C.c_size_t)]
+        L.oci_setup.argtypes = [D, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.oci_set_state.argtypes = [vp, vp]
+        L.oci_get_state.argtypes = [vp, vp]
+        L.oci_step.argtypes = [vp] * 7
+        L.si_step.argtypes = [vp] * 7
+        L.oci_profile_enable.argtypes = [vp, i32]
+        L.oci_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.oci_destroy.argtypes = [vp]
+        L.oci_status_string.argtypes = [i32]
+        L.oci_status_string.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("oci_status_string",):
+                getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _ptr(x):
+    """Device/host pointer of a torch tensor, numpy array, int or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(type(x))
+
+
+def _check(call, rc):
+    if rc < 0:
+        raise OciError(call, rc)
+    return rc
+
+
+def oci_status_string(code):
+    return lib().oci_status_string(int(code)).decode()
+
+
+def make_desc(prob, tol=1e-10, max_iters=100000, fixed_iters=0,
+              precision=OCI_FP64, norm=OCI_NORM_SCALAR, dt=None):
+    """Build an oci_desc from a workload dict; the returned keep-alive tuple
+    holds the host arrays the descriptor points to."""
+    arrs = tuple(np.ascontiguousarray(prob[k], dtype=np.float64)
+                 for k in ("dx", "sigma_t", "sigma_s", "speed"))
+    d = oci_desc(int(prob["J"]), int(prob["N"]), int(prob["G"]),
+                 *[a.ctypes.data for a in arrs],
+                 float(prob["dt"] if dt is None else dt), float(tol), int(max_iters),
+                 int(fixed_iters), int(precision), int(norm))
+    return d, arrs
+
+
+def oci_workspace_bytes(desc):
+    n = C.c_size_t(0)
+    _check("oci_workspace_bytes", lib().oci_workspace_bytes(C.byref(desc), C.byref(n)))
+    return n.value
+
+
+def oci_setup(desc, workspace, nbytes, stream=None):
+    h = C.c_void_p()
+    _check("oci_setup", lib().oci_setup(C.byref(desc), _ptr(workspace), int(nbytes),
+                                        _ptr(stream), C.byref(h)))
+    return h
+
+
+def oci_set_state(h, psi_prev):
+    _check("oci_set_state", lib().oci_set_state(h, _ptr(psi_prev)))
+
+
+def oci_get_state(h, psi_prev):
+    _check("oci_get_state", lib().oci_get_state(h, _ptr(psi_prev)))
+
+
+def oci_step(h, q, inc_left, inc_right, phi_out, psi_out, info):
+    return _check("oci_step", lib().oci_step(h, _ptr(q), _ptr(inc_left), _ptr(inc_right),
+                                             _ptr(phi_out), _ptr(psi_out), _ptr(info)))
+
+
+def si_step(h, q, inc_left, inc_right, phi_out, psi_out, info):
+    return _check("si_step", lib().si_step(h, _ptr(q), _ptr(inc_left), _ptr(inc_right),
+                                           _ptr(phi_out), _ptr(psi_out), _ptr(info)))
+
+
+def oci_profile_enable(h, on=True):
+    _check("oci_profile_enable", lib().oci_profile_enable(h, 1 if on else 0))
+
+
+def oci_profile_read(h):
+    """(milliseconds of iteration kernels, steps recorded) since the last read."""
+    ms, n = C.c_double(0.0), C.c_int32(0)
+    _check("oci_profile_read", lib().oci_profile_read(h, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def oci_destroy(h):
+    _check("oci_destroy", lib().oci_destroy(h))
+
+
+def decode_info(raw):
+    """oci_step_info from its 24 bytes (numpy uint8 array or bytes)."""
+    b = bytes(np.asarray(raw, dtype=np.uint8).tobytes())
+    info = oci_step_info.from_buffer_copy(b[:C.sizeof(oci_step_info)])
+    return dict(iterations=info.iterations, status=info.status,
+                e_last=info.e_last, rho_e=info.rho_e)
+
+
+class Solver:
+    """Device buffers for one slab problem plus the liboci handle.
+
+    prob: a workload dict (see workloads.py).  All arrays are copied to the
+    current CUDA (HIP) device; steps run on torch's current stream.
+    """
+
+    def __init__(self, prob, precision=OCI_FP64, tol=1e-10, max_iters=100000,
+                 fixed_iters=0, norm=OCI_NORM_SCALAR, stream=None, dt=None):
+        import torch
+        self.torch = torch
+        self.prob = prob
+        self.J, self.N, self.G = prob["J"], prob["N"], prob["G"]
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        self.desc, self._keep = make_desc(prob, tol=tol, max_iters=max_iters,
+                                          fixed_iters=fixed_iters, precision=precision,
+                                          norm=norm, dt=dt)
+        self.ws_bytes = oci_workspace_bytes(self.desc)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = self.ws.data_ptr() + off
+        self.h = oci_setup(self.desc, self.ws_ptr, self.ws_bytes, self.stream.cuda_stream)
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.phi = torch.empty((self.J, self.G, 4), **f64)
+        self.psi = torch.empty((self.J, self.G, self.N, 4), **f64)
+        self.info = torch.zeros(32, dtype=torch.uint8, device=self.dev)
+        self.set_inputs(prob.get("q"), prob.get("inc_left"), prob.get("inc_right"))
+        if prob.get("psi_init") is not None and np.any(prob["psi_init"]):
+            self.set_state(prob["psi_init"])
+
+    def _dev(self, a):
+        if a is None:
+            return None
+        return self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(self.dev)
+
+    def set_inputs(self, q=None, inc_left=None, inc_right=None):
+        self.q, self.inc_l, self.inc_r = self._dev(q), self._dev(inc_left), self._dev(inc_right)
+
+    def set_state(self, psi_prev):
+        self._state = self._dev(psi_prev)
+        oci_set_state(self.h, self._state)
+
+    def get_state(self):
+        out = self.torch.empty((self.J, self.G, self.N, 2), dtype=self.torch.float64, device=self.dev)
+        oci_get_state(self.h, out)
+        return out
+
+    def step(self, method="oci", want_psi=False):
+        fn = oci_step if method == "oci" else si_step
+        fn(self.h, self.q, self.inc_l, self.inc_r, self.phi,
+           self.psi if want_psi else None, self.info)
+
+    def last_info(self):
+        self.stream.synchronize()
+        return decode_info(self.info.cpu().numpy())
+
+    def run(self, steps=None, method="oci", want_psi=False):
+        """Run steps; returns (phi per step [steps][J][G][4], infos)."""
+        steps = self.prob["steps"] if steps is None else steps
+        phis, infos = [], []
+        for _ in range(steps):
+            self.step(method, want_psi)
+            phis.append(self.phi.clone())
+            infos.append(self.info.clone())
+        self.stream.synchronize()
+        return (self.torch.stack(phis).cpu().numpy(),
+                [decode_info(i.cpu().numpy()) for i in infos])
+
+    def close(self):
+        if self.h is not None:
+            self.stream.synchronize()
+            oci_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

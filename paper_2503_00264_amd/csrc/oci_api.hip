@@ -1,0 +1,410 @@
+// oci_api.hip -- host side of the liboci C ABI (include/oci.h): argument
+// validation, quadrature, workspace layout and the launch sequence of setup
+// and time steps.  Every step of the method runs in the device kernels of
+// oci_setup.hip and oci_step.hip; nothing here computes on the host beyond
+// the quadrature rule and launch geometry.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/oci.h"
+#include "oci_internal.hpp"
+
+namespace oci {
+hipError_t launch_setup(const Slab &S, bool fp32, hipStream_t st);
+hipError_t launch_begin(const Slab &S, bool broadcast_state, hipStream_t st);
+hipError_t launch_end(const Slab &S, const StepIO &io, hipStream_t st);
+hipError_t launch_oci_step(const Slab &S, const StepIO &io, bool fp32, int np, bool res, int bs, int nwg, int ntiles,
+                           hipStream_t st, bool cooperative);
+hipError_t oci_occupancy(bool fp32, int np, bool res, int bs, int *blocks);
+bool resident_supported(bool fp32, int np);
+bool block_supported(int bs);
+hipError_t launch_si_iteration(const Slab &S, const StepIO &io, hipStream_t st);
+size_t si_flux_blocks(const Slab &S);
+}  // namespace oci
+
+using namespace oci;
+
+struct oci_handle {
+    oci_desc d;            // scalars only (host pointers cleared)
+    int n, np;             // 4 N G and its padded power of two
+    bool fp32;
+    hipStream_t st;
+    int device, num_cu;
+    Slab S;
+    unsigned char *ws;
+    size_t ws_bytes;
+    int nwg, ntiles;       // OCI persistent launch geometry
+    int block;             // threads per workgroup of the OCI kernel
+    bool resident;
+    bool need_broadcast;   // next step starts from psi_prev on both levels
+    int32_t *h_flag;       // pinned host word for SI's convergence polling
+    bool profiling;
+    std::vector<hipEvent_t> ev_pool;   // recorded pairs: [2k] start, [2k+1] stop
+    size_t ev_used;
+};
+
+// Two events bracketing the iteration kernels of one step (instrumentation).
+static hipEvent_t prof_event(oci_handle *h) {
+    if (h->ev_used == h->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->ev_pool.push_back(e);
+    }
+    return h->ev_pool[h->ev_used++];
+}
+
+// ------------------------------------------------------------- validation
+static bool finite_nonneg(const double *a, size_t n, bool strictly_pos) {
+    for (size_t i = 0; i < n; ++i) {
+        if (!isfinite(a[i])) return false;
+        if (strictly_pos ? !(a[i] > 0.0) : !(a[i] >= 0.0)) return false;
+    }
+    return true;
+}
+
+static int pad_pow2(int n) {
+    int p = 8;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+static int check_desc(const oci_desc *d) {
+    if (!d) return OCI_ERR_INVALID;
+    if (d->J < 1 || d->N < 2 || (d->N & 1) || d->G < 1) return OCI_ERR_INVALID;
+    if ((long)4 * d->N * d->G > kMaxN) return OCI_ERR_UNSUPPORTED;
+    if (!d->dx || !d->sigma_t || !d->sigma_s || !d->speed) return OCI_ERR_INVALID;
+    if (!(d->dt > 0.0) || !isfinite(d->dt)) return OCI_ERR_INVALID;
+    if (!(d->tol >= 0.0) || !isfinite(d->tol)) return OCI_ERR_INVALID;
+    if (d->max_iters < 1 || d->fixed_iters < 0) return OCI_ERR_INVALID;
+    if (d->precision != OCI_FP64 && d->precision != OCI_FP32_REFINED) return OCI_ERR_INVALID;
+    if (d->norm != OCI_NORM_SCALAR && d->norm != OCI_NORM_ANGULAR) return OCI_ERR_INVALID;
+    const size_t J = d->J, G = d->G;
+    if (!finite_nonneg(d->dx, J, true)) return OCI_ERR_INVALID;
+    if (!finite_nonneg(d->sigma_t, J * G, false)) return OCI_ERR_INVALID;
+    if (!finite_nonneg(d->sigma_s, J * G * G, false)) return OCI_ERR_INVALID;
+    if (!finite_nonneg(d->speed, G, true)) return OCI_ERR_INVALID;
+    return OCI_OK;
+}
+
+// ------------------------------------------------------------- quadrature
+// Gauss-Legendre nodes (ascending) and weights: Newton's method on P_N from
+// Tricomi's asymptotic guess, weights 2 / ((1 - x^2) P_N'(x)^2); the negative
+// half mirrors the positive half so the rule is exactly symmetric.
+static void gauss_legendre(int N, double *mu, double *w) {
+    const int h = N / 2;
+    for (int k = 1; k <= h; ++k) {
+        const double th = M_PI * (4.0 * k - 1.0) / (4.0 * N + 2.0);
+        double x = (1.0 - 1.0 / (8.0 * N * N) + 1.0 / (8.0 * (double)N * N * N)) * cos(th);
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double pm = 1.0, p = x;
+            for (int l = 2; l <= N; ++l) {
+                const double pn = ((2 * l - 1) * x * p - (l - 1) * pm) / l;
+                pm = p;
+                p = pn;
+            }
+            dp = N * (x * p - pm) / (x * x - 1.0);
+            const double dx = p / dp;
+            x -= dx;
+            if (fabs(dx) <= 1e-16) break;
+        }
+        double pm = 1.0, p = x;
+        for (int l = 2; l <= N; ++l) {
+            const double pn = ((2 * l - 1) * x * p - (l - 1) * pm) / l;
+            pm = p;
+            p = pn;
+        }
+        dp = N * (x * p - pm) / (x * x - 1.0);
+        const double wk = 2.0 / ((1.0 - x * x) * dp * dp);
+        // k = 1 is the largest root
+        mu[N - k] = x;
+        w[N - k] = wk;
+        mu[k - 1] = -x;
+        w[k - 1] = wk;
+    }
+}
+
+// --------------------------------------------------------------- workspace
+struct Layout {
+    size_t ctl, bar, mu, w, dx, st, ss, sp, X, psi0, psi1, phi0, phi1, prev, linv, part, total;
+    int bar_groups;
+};
+
+static int device_cus() {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) return 256;
+    return cu;
+}
+
+static Layout layout(const oci_desc *d, int num_cu) {
+    const size_t J = d->J, N = d->N, G = d->G, n = 4 * N * G;
+    const size_t np = pad_pow2((int)n);
+    const size_t es = d->precision == OCI_FP32_REFINED ? 4 : 8;
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    L.ctl = take(sizeof(Ctl));
+    L.bar_groups = (num_cu * 8 + kBarGroup - 1) / kBarGroup;
+    L.bar = take((size_t)(2 + L.bar_groups) * kBarStride * 8);
+    L.mu = take(N * 8);
+    L.w = take(N * 8);
+    L.dx = take(J * 8);
+    L.st = take(J * G * 8);
+    L.ss = take(J * G * G * 8);
+    L.sp = take(G * 8);
+    L.X = take(J * np * np * es);
+    L.psi0 = take(J * n * 8);
+    L.psi1 = take(J * n * 8);
+    L.phi0 = take(J * G * 4 * 8);
+    L.phi1 = take(J * G * 4 * 8);
+    L.prev = take(J * n / 2 * 8);
+    L.linv = take(J * G * N * 16 * 8);
+    const size_t si_blocks = (J * G * 4 + kBlock - 1) / kBlock;
+    size_t parts = (size_t)num_cu * 8;
+    if (si_blocks > parts) parts = si_blocks;
+    L.part = take(parts * 8);
+    L.total = o;
+    return L;
+}
+
+extern "C" int oci_workspace_bytes(const oci_desc *desc, size_t *bytes) {
+    const int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!bytes) return OCI_ERR_INVALID;
+    *bytes = layout(desc, device_cus()).total;
+    return OCI_OK;
+}
+
+#define HIPCHECK(x)                                  \
+    do {                                             \
+        if ((x) != hipSuccess) return OCI_ERR_HIP;   \
+    } while (0)
+
+extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t workspace_bytes, void *stream,
+                         oci_handle **out) {
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!out) return OCI_ERR_INVALID;
+    *out = nullptr;
+    const int num_cu = device_cus();
+    const Layout L = layout(desc, num_cu);
+    if (!workspace_dev || ((uintptr_t)workspace_dev & 255) || workspace_bytes < L.total) return OCI_ERR_WORKSPACE;
+
+    oci_handle *h = new (std::nothrow) oci_handle();
+    if (!h) return OCI_ERR_HIP;
+    h->d = *desc;
+    h->d.dx = h->d.sigma_t = h->d.sigma_s = h->d.speed = nullptr;
+    h->n = 4 * desc->N * desc->G;
+    h->np = pad_pow2(h->n);
+    h->fp32 = desc->precision == OCI_FP32_REFINED;
+    h->st = (hipStream_t)stream;
+    h->num_cu = num_cu;
+    h->ws = (unsigned char *)workspace_dev;
+    h->ws_bytes = workspace_bytes;
+    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return OCI_ERR_HIP; }
+    if (hipHostMalloc((void **)&h->h_flag, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        return OCI_ERR_HIP;
+    }
+
+    unsigned char *ws = h->ws;
+    Slab &S = h->S;
+    S.J = desc->J; S.N = desc->N; S.G = desc->G; S.n = h->n; S.np = h->np;
+    S.dt = desc->dt;
+    S.mu = (const double *)(ws + L.mu);
+    S.w = (const double *)(ws + L.w);
+    S.dx = (const double *)(ws + L.dx);
+    S.sigma_t = (const double *)(ws + L.st);
+    S.sigma_s = (const double *)(ws + L.ss);
+    S.speed = (const double *)(ws + L.sp);
+    S.X = ws + L.X;
+    S.psi[0] = (double *)(ws + L.psi0);
+    S.psi[1] = (double *)(ws + L.psi1);
+    S.phi[0] = (double *)(ws + L.phi0);
+    S.phi[1] = (double *)(ws + L.phi1);
+    S.psi_prev = (double *)(ws + L.prev);
+    S.si_linv = (double *)(ws + L.linv);
+    S.partials = (double *)(ws + L.part);
+    S.ctl = (Ctl *)(ws + L.ctl);
+    S.bar = (uint64_t *)(ws + L.bar);
+    S.bar_groups = L.bar_groups;
+    S.tol = desc->tol;
+    S.max_iters = desc->max_iters;
+    S.fixed_iters = desc->fixed_iters;
+    S.norm = desc->norm;
+    S.refined = h->fp32 ? 1 : 0;
+
+    double *mu = (double *)malloc(sizeof(double) * desc->N * 2);
+    if (!mu) { oci_destroy(h); return OCI_ERR_HIP; }
+    gauss_legendre(desc->N, mu, mu + desc->N);
+    const size_t J = desc->J, G = desc->G;
+    hipError_t e = hipSuccess;
+    hipStream_t st = h->st;
+    auto up = [&](size_t off, const void *src, size_t bytes) {
+        if (e == hipSuccess) e = hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    up(L.mu, mu, desc->N * 8);
+    up(L.w, mu + desc->N, desc->N * 8);
+    up(L.dx, desc->dx, J * 8);
+    up(L.st, desc->sigma_t, J * G * 8);
+    up(L.ss, desc->sigma_s, J * G * G * 8);
+    up(L.sp, desc->speed, G * 8);
+    if (e == hipSuccess) e = hipMemsetAsync(ws + L.ctl, 0, L.mu - L.ctl, st);
+    if (e == hipSuccess) e = hipMemsetAsync(ws + L.psi0, 0, L.prev + J * h->n / 2 * 8 - L.psi0, st);
+    if (e == hipSuccess) e = launch_setup(S, h->fp32, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    free(mu);
+    if (e != hipSuccess) { oci_destroy(h); return OCI_ERR_HIP; }
+    Ctl c;
+    if (hipMemcpy(&c, S.ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) { oci_destroy(h); return OCI_ERR_HIP; }
+    if (c.singular) { oci_destroy(h); return OCI_ERR_SINGULAR; }
+
+    // persistent launch geometry: one tile = block / (threads per cell) cells;
+    // OCI_BLOCK (256 or 1024) overrides the block size
+    h->block = 1024;
+    if (const char *env = getenv("OCI_BLOCK")) {
+        const int b = atoi(env);
+        if (block_supported(b)) h->block = b;
+    }
+    const int rpt = h->np > h->block ? h->np / h->block : 1;
+    const int tpc = h->np / rpt;
+    const int cpt = h->block / tpc;
+    h->ntiles = (desc->J + cpt - 1) / cpt;
+    int occ_res = 0, occ = 0;
+    if (oci_occupancy(h->fp32, h->np, false, h->block, &occ) != hipSuccess || occ < 1) {
+        oci_destroy(h);
+        return OCI_ERR_HIP;
+    }
+    const long wg_cap = (long)num_cu * 8;  // partial-sum slots in the workspace
+    h->resident = false;
+    const char *nores = getenv("OCI_NO_RESIDENT");
+    if (!(nores && atoi(nores)) && resident_supported(h->fp32, h->np) &&
+        oci_occupancy(h->fp32, h->np, true, h->block, &occ_res) == hipSuccess &&
+        (long)occ_res * num_cu >= h->ntiles && h->ntiles <= wg_cap) {
+        h->resident = true;
+        h->nwg = h->ntiles;
+    } else {
+        const long cap = (long)occ * num_cu;
+        h->nwg = (int)(h->ntiles < cap ? h->ntiles : cap);
+    }
+    if (h->nwg > wg_cap) h->nwg = (int)wg_cap;
+    h->need_broadcast = true;
+    *out = h;
+    return OCI_OK;
+}
+
+extern "C" int oci_set_state(oci_handle *h, const double *psi_prev_dev) {
+    if (!h) return OCI_ERR_INVALID;
+    const size_t bytes = (size_t)h->d.J * h->n / 2 * 8;
+    hipError_t e = psi_prev_dev ? hipMemcpyAsync(h->S.psi_prev, psi_prev_dev, bytes, hipMemcpyDeviceToDevice, h->st)
+                                : hipMemsetAsync(h->S.psi_prev, 0, bytes, h->st);
+    if (e != hipSuccess) return OCI_ERR_HIP;
+    h->need_broadcast = true;
+    return OCI_OK;
+}
+
+extern "C" int oci_get_state(const oci_handle *h, double *psi_prev_dev) {
+    if (!h || !psi_prev_dev) return OCI_ERR_INVALID;
+    const size_t bytes = (size_t)h->d.J * h->n / 2 * 8;
+    if (hipMemcpyAsync(psi_prev_dev, h->S.psi_prev, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess)
+        return OCI_ERR_HIP;
+    return OCI_OK;
+}
+
+static int check_step_args(oci_handle *h, double *phi_out_dev, oci_step_info *info_dev) {
+    if (!h || !phi_out_dev || !info_dev) return OCI_ERR_INVALID;
+    return OCI_OK;
+}
+
+extern "C" int oci_step(oci_handle *h, const double *q_dev, const double *inc_left_dev, const double *inc_right_dev,
+                        double *phi_out_dev, double *psi_out_dev, oci_step_info *info_dev) {
+    int rc = check_step_args(h, phi_out_dev, info_dev);
+    if (rc) return rc;
+    StepIO io{q_dev, inc_left_dev, inc_right_dev, phi_out_dev, psi_out_dev, info_dev};
+    HIPCHECK(launch_begin(h->S, h->need_broadcast, h->st));
+    h->need_broadcast = false;
+    hipEvent_t e0 = h->profiling ? prof_event(h) : nullptr, e1 = h->profiling ? prof_event(h) : nullptr;
+    if (e0) HIPCHECK(hipEventRecord(e0, h->st));
+    HIPCHECK(launch_oci_step(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->st, true));
+    if (e1) HIPCHECK(hipEventRecord(e1, h->st));
+    HIPCHECK(launch_end(h->S, io, h->st));
+    return OCI_OK;
+}
+
+extern "C" int si_step(oci_handle *h, const double *q_dev, const double *inc_left_dev, const double *inc_right_dev,
+                       double *phi_out_dev, double *psi_out_dev, oci_step_info *info_dev) {
+    int rc = check_step_args(h, phi_out_dev, info_dev);
+    if (rc) return rc;
+    StepIO io{q_dev, inc_left_dev, inc_right_dev, phi_out_dev, psi_out_dev, info_dev};
+    HIPCHECK(launch_begin(h->S, h->need_broadcast, h->st));
+    h->need_broadcast = false;
+    // the iterations stop themselves on the device; the host only polls the
+    // done flag between growing batches of launches
+    const int cap = h->d.fixed_iters > 0 ? h->d.fixed_iters : h->d.max_iters;
+    hipEvent_t e0 = h->profiling ? prof_event(h) : nullptr, e1 = h->profiling ? prof_event(h) : nullptr;
+    if (e0) HIPCHECK(hipEventRecord(e0, h->st));
+    int launched = 0, batch = 4;
+    for (;;) {
+        const int k = (cap - launched) < batch ? (cap - launched) : batch;
+        for (int i = 0; i < k; ++i) HIPCHECK(launch_si_iteration(h->S, io, h->st));
+        launched += k;
+        if (launched >= cap) break;
+        HIPCHECK(hipMemcpyAsync(h->h_flag, &h->S.ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+        HIPCHECK(hipStreamSynchronize(h->st));
+        if (*h->h_flag) break;
+        if (batch < 64) batch *= 2;
+    }
+    if (e1) HIPCHECK(hipEventRecord(e1, h->st));
+    HIPCHECK(launch_end(h->S, io, h->st));
+    return OCI_OK;
+}
+
+extern "C" int oci_profile_enable(oci_handle *h, int on) {
+    if (!h) return OCI_ERR_INVALID;
+    h->profiling = on != 0;
+    h->ev_used = 0;
+    return OCI_OK;
+}
+
+extern "C" int oci_profile_read(oci_handle *h, double *ms, int32_t *steps) {
+    if (!h || !ms || !steps) return OCI_ERR_INVALID;
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+        float t = 0.f;
+        if (hipEventSynchronize(h->ev_pool[k + 1]) != hipSuccess) return OCI_ERR_HIP;
+        if (hipEventElapsedTime(&t, h->ev_pool[k], h->ev_pool[k + 1]) != hipSuccess) return OCI_ERR_HIP;
+        tot += t;
+    }
+    *ms = tot;
+    *steps = (int32_t)(h->ev_used / 2);
+    h->ev_used = 0;
+    return OCI_OK;
+}
+
+extern "C" int oci_destroy(oci_handle *h) {
+    if (!h) return OCI_ERR_INVALID;
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->h_flag) (void)hipHostFree(h->h_flag);
+    delete h;
+    return OCI_OK;
+}
+
+extern "C" const char *oci_status_string(int s) {
+    switch (s) {
+    case OCI_OK: return "ok";
+    case OCI_NOT_CONVERGED: return "not converged (iteration cap reached)";
+    case OCI_NONFINITE: return "non-finite change (iteration diverged or bad input)";
+    case OCI_ERR_INVALID: return "invalid argument";
+    case OCI_ERR_HIP: return "HIP runtime error";
+    case OCI_ERR_SINGULAR: return "singular cell matrix (zero pivot)";
+    case OCI_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case OCI_ERR_UNSUPPORTED: return "cell system larger than the compiled kernels (4 N G > 512)";
+    case OCI_ERR_DEVICE: return "device guard tripped (grid barrier did not complete)";
+    default: return "unknown status";
+    }
+}

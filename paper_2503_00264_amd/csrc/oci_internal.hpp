@@ -1,0 +1,87 @@
+// oci_internal.hpp -- layouts and launch parameters shared by the host side of
+// liboci and its gfx950 kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace oci {
+
+// Largest cell system the kernels are compiled for (n = 4 N G).
+constexpr int kMaxN = 512;
+// Threads per workgroup of the setup and bookkeeping kernels.
+constexpr int kBlock = 256;
+// Barrier words are kBarStride uint64 apart; workgroups arrive in groups of
+// kBarGroup before one leader per group arrives at the top counter.
+constexpr int kBarStride = 32;
+constexpr int kBarGroup = 16;
+
+// Control block of one slab problem, in the workspace.  Written by the step
+// kernels only; the host reads `done` to learn that a step has stopped.
+struct Ctl {
+    int32_t base;          // ping-pong index holding the first iterate of the step
+    int32_t iter;          // iterations performed in the current step
+    int32_t done;          // 1 once the current step has stopped
+    int32_t status;        // OCI_OK / OCI_NOT_CONVERGED / OCI_NONFINITE
+    int32_t err;           // device guard tripped (OCI_ERR_DEVICE)
+    int32_t singular;      // setup found a zero pivot
+    uint32_t bar_count;    // grid barrier: arrivals in the current generation
+    uint32_t bar_gen;      // grid barrier: generation
+    double e_prev;         // e_{l-1}
+    double e_last;         // e_l
+    double rho;            // e_l / e_{l-1}
+    double pad[3];
+};
+static_assert(sizeof(Ctl) == 80, "Ctl layout");
+
+// Device-side view of one slab problem (all pointers into the workspace or
+// caller memory).  Passed by value to every kernel.
+struct Slab {
+    int32_t J, N, G, n;          // n = 4 N G
+    int32_t np;                  // n padded to a power of two >= 8 (factor block size)
+    double dt;
+    const double *mu, *w;        // [N] ascending Gauss-Legendre nodes / weights
+    const double *dx;            // [J]
+    const double *sigma_t;       // [J][G]
+    const double *sigma_s;       // [J][G][G], [j][g][gp] = gp -> g
+    const double *speed;         // [G]
+    void *X;                     // [J][np][np] inverse of A_j (identity-padded), tiled (see xoff)
+    double *psi[2];              // [J][G][N][4] ping-pong iterates
+    double *phi[2];              // [J][G][4]   scalar flux of each iterate
+    double *psi_prev;            // [J][G][N][2] state psi_{k-1/2}
+    double *si_linv;             // [J][G][N][16] inverse of the 4x4 SI cell matrix
+    double *partials;            // [max workgroups] per-workgroup sums
+    Ctl *ctl;
+    // grid barrier words, 256 bytes apart: [0] arrivals of group leaders,
+    // [kBarStride] release flag, [(2 + k) * kBarStride] arrivals in group k
+    uint64_t *bar;
+    int32_t bar_groups;          // group counters present in `bar`
+    // step controls
+    double tol;
+    int32_t max_iters, fixed_iters, norm, refined;
+};
+
+// Per-step inputs (caller memory).
+struct StepIO {
+    const double *q;             // [J][G][4] or null
+    const double *inc_l;         // [2][G][N/2] or null
+    const double *inc_r;         // [2][G][N/2] or null
+    double *phi_out;             // [J][G][4]
+    double *psi_out;             // [J][G][N][4] or null
+    void *info;                  // oci_step_info*
+};
+
+// Element (r, c) of a cell's n x n factor block, stored as 16-byte vectors
+// along rows: block [c / V][r][c % V], V = 16 / sizeof(T).  The thread that
+// owns row r reads columns c .. c+V-1 with one 16-byte load, and the threads
+// of consecutive rows read consecutive 16-byte words.
+template <typename T>
+__host__ __device__ inline size_t xoff(int n, int r, int c) {
+    constexpr int V = 16 / sizeof(T);
+    return ((size_t)(c / V) * n + r) * V + (c % V);
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace oci

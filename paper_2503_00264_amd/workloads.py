@@ -3,8 +3,8 @@
 This module draws the material data, cell widths, sources and time-step
 settings of the slab transport problems that exercise the one-cell-inversion
 (OCI) and source-iteration (SI) solvers.  It holds none of the method's
-arithmetic: no discretisation, no quadrature, no solve.  Both the CPU oracle
-(through the tests) and the GPU library are fed from the arrays built here.
+arithmetic: no discretisation, no quadrature, no solve.  The GPU library and
+the tests' independent CPU reference are fed from the same arrays built here.
 
 Every problem is a dict of plain numpy arrays (float64 unless noted):
 

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances (see the design notes for the derivation):
+  * FP64 OCI / SI in lock-step (the same fixed number of iterations per step
+    on both sides): normwise relative difference of every step's scalar flux
+    <= 1e-12.  Both sides solve the same systems; they differ only in
+    rounding order (an explicit inverse against forward/back substitution,
+    fused multiply-adds, tree against serial sums), each ~kappa * 1e-16 per
+    solve with kappa <= ~200 for these cell matrices.
+  * FP32-refined OCI converged to tol on the GPU against the oracle converged
+    to 1e-14: <= 1e-10 normwise relative.  Both share the fixed point; the
+    refined iteration adds a contraction of ~kappa * 6e-8 per step.
+Every case prints its name, shape and seed before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_00264_amd import binding as B
+from paper_2503_00264_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    B.lib()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _cases():
+    return {
+        # name: (problem, steps)
+        "homogeneous64_n32": (W.config("homogeneous64"), 3),
+        "regions512_n64": (W.regions(seed=2, J=512, N=16, n_regions=64, length=8.0, dt=0.1), 3),
+        "multigroup192_n128": (W.multigroup(seed=3, J=192, N=8, G=4, n_regions=64, length=1.5,
+                                            dt=1e-3), 2),
+        "multigroup128_n256": (W.multigroup(seed=4, J=128, N=16, G=4, n_regions=64, length=1.0,
+                                            dt=1e-3), 2),
+        "multigroup40_n512": (W.multigroup(seed=5, J=40, N=32, G=4, n_regions=8, length=0.625,
+                                           dt=1e-3), 2),
+        "odd_N6_n24": (W.regions(seed=6, J=77, N=6, n_regions=7, length=3.0, dt=0.2), 2),
+        "G3_n48": (W.multigroup(seed=7, J=45, N=4, G=3, n_regions=5, length=2.0,
+                                speeds=(5.0, 1.0, 0.2), dt=0.3), 2),
+        "single_cell": (W.multigroup(seed=8, J=1, N=8, G=2, n_regions=1, length=0.5,
+                                     speeds=(2.0, 1.0), dt=0.1), 2),
+        "N2_J5": (W.homogeneous(J=5, N=2, length=1.0), 2),
+    }
+
+
+CASES = _cases()
+
+
+def _announce(name, p, extra=""):
+    print(f"\n[gpu case] {name}: J={p['J']} N={p['N']} G={p['G']} n={4 * p['N'] * p['G']} {extra}",
+          flush=True)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_oci_fp64_lockstep(name):
+    p, steps = CASES[name]
+    K = 7
+    _announce(name, p, f"oci fp64 lock-step K={K} steps={steps}")
+    want = oracle.Oracle(p).run("oci", steps=steps, fixed_iters=K)["phi"]
+    s = B.Solver(p, precision=B.OCI_FP64, fixed_iters=K)
+    got, infos = s.run(steps=steps, want_psi=True)
+    s.close()
+    assert all(i["iterations"] == K and i["status"] == 0 for i in infos), infos
+    assert rel(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["homogeneous64_n32", "regions512_n64", "multigroup192_n128",
+                                  "G3_n48", "single_cell", "N2_J5"])
+def test_si_fp64_lockstep(name):
+    p, steps = CASES[name]
+    K = 5
+    _announce(name, p, f"si fp64 lock-step K={K}")
+    want = oracle.Oracle(p).run("si", steps=steps, fixed_iters=K)["phi"]
+    s = B.Solver(p, precision=B.OCI_FP64, fixed_iters=K)
+    got, infos = s.run(steps=steps, method="si")
+    s.close()
+    assert all(i["iterations"] == K and i["status"] == 0 for i in infos), infos
+    assert rel(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["homogeneous64_n32", "regions512_n64", "multigroup192_n128",
+                                  "multigroup128_n256", "multigroup40_n512", "G3_n48"])
+def test_oci_refined_converges_to_oracle(name):
+    p, steps = CASES[name]
+    _announce(name, p, "oci fp32-refined converged")
+    want = oracle.Oracle(p).run("oci", steps=steps, tol=1e-14)["phi"]
+    s = B.Solver(p, precision=B.OCI_FP32_REFINED, tol=1e-12)
+    got, infos = s.run(steps=steps)
+    s.close()
+    assert all(i["status"] == 0 for i in infos), infos
+    assert rel(got, want) <= 1e-10
+
+
+def test_oci_fp64_converged_iteration_counts_match():
+    p = W.config("homogeneous64")
+    _announce("homogeneous64", p, "converged, 10 steps, tol 1e-10")
+    ref = oracle.Oracle(p).run("oci", tol=1e-10)
+    s = B.Solver(p, precision=B.OCI_FP64, tol=1e-10)
+    got, infos = s.run()
+    s.close()
+    assert [i["iterations"] for i in infos] == [i["iterations"] for i in ref["info"]]
+    assert rel(got, ref["phi"]) <= 1e-12
+    # e_l is a norm of differences of nearly equal iterates: each entry
+    # carries ~1e-16 |phi| of rounding, so compare on that absolute scale
+    scale = 1e-14 * np.max(np.abs(ref["phi"])) * np.sqrt(ref["phi"][0].size)
+    for a, b in zip(infos, ref["info"]):
+        assert abs(a["e_last"] - b["e_last"]) <= scale
+        assert abs(a["rho_e"] - b["rho_e"]) <= 1e-3
+
+
+def test_angular_norm_counts_match():
+    p = W.regions(seed=2, J=256, N=8, n_regions=64, length=4.0, dt=0.05, steps=2)
+    _announce("regions256", p, "angular norm")
+    ref = oracle.Oracle(p).run("oci", tol=1e-9, norm=oracle.NORM_ANGULAR)
+    s = B.Solver(p, precision=B.OCI_FP64, tol=1e-9, norm=B.OCI_NORM_ANGULAR)
+    got, infos = s.run()
+    s.close()
+    assert [i["iterations"] for i in infos] == [i["iterations"] for i in ref["info"]]
+    assert rel(got, ref["phi"]) <= 1e-12
+
+
+def test_boundary_sources_and_initial_state():
+    p = W.multigroup(seed=9, J=96, N=8, G=2, n_regions=8, length=2.0, speeds=(3.0, 1.0), dt=0.2,
+                     steps=3)
+    rng = np.random.default_rng(21)
+    p["inc_left"] = rng.uniform(0, 1, size=(2, 2, 4))
+    p["inc_right"] = rng.uniform(0, 1, size=(2, 2, 4))
+    p["psi_init"] = rng.uniform(0, 1, size=(96, 2, 8, 2))
+    _announce("boundary", p, "incident fluxes + initial state")
+    for method in ("oci", "si"):
+        want = oracle.Oracle(p).run(method, fixed_iters=6)
+        s = B.Solver(p, precision=B.OCI_FP64, fixed_iters=6)
+        got, _ = s.run(method=method)
+        state = s.get_state().cpu().numpy()
+        s.close()
+        assert rel(got, want["phi"]) <= 1e-12
+        assert rel(state, want["psi_prev"]) <= 1e-12
+
+
+def test_oci_and_si_agree_on_gpu():
+    p = W.regions(seed=2, J=512, N=16, n_regions=64, length=8.0, dt=0.05, steps=2)
+    _announce("regions512", p, "oci vs si converged")
+    a = B.Solver(p, tol=1e-13)
+    pa, _ = a.run()
+    a.close()
+    b = B.Solver(p, tol=1e-13)
+    pb, _ = b.run(method="si")
+    b.close()
+    assert rel(pa, pb) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", [B.OCI_FP64, B.OCI_FP32_REFINED])
+def test_run_twice_bitwise(prec):
+    p = W.regions(seed=2, J=1024, N=16, n_regions=64, length=16.0, dt=0.01, steps=3)
+    _announce("regions1024", p, f"determinism prec={prec}")
+    out = []
+    for _ in range(2):
+        s = B.Solver(p, precision=prec, tol=1e-10)
+        got, infos = s.run()
+        s.close()
+        out.append((got, [i["iterations"] for i in infos]))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
+def test_status_not_converged_and_nonfinite():
+    p = W.homogeneous(J=64, N=8)
+    _announce("homogeneous64", p, "statuses")
+    s = B.Solver(p, max_iters=3, tol=1e-10)
+    _, infos = s.run(steps=1)
+    s.close()
+    assert infos[0]["status"] == B.OCI_NOT_CONVERGED and infos[0]["iterations"] == 3
+    q = p["q"].copy()
+    q[10, 0, 2] = np.nan
+    p2 = dict(p, q=q)
+    s = B.Solver(p2, tol=1e-10)
+    _, infos = s.run(steps=1)
+    s.close()
+    assert infos[0]["status"] == B.OCI_NONFINITE and infos[0]["iterations"] == 1
+
+
+def test_state_roundtrip_restart():
+    p = W.regions(seed=2, J=256, N=8, n_regions=64, length=4.0, dt=0.05, steps=4)
+    _announce("regions256", p, "checkpoint / restart")
+    a = B.Solver(p, fixed_iters=5)
+    full, _ = a.run(steps=4)
+    a.close()
+    b = B.Solver(p, fixed_iters=5)
+    b.run(steps=2)
+    st = b.get_state().cpu().numpy()
+    b.close()
+    c = B.Solver(p, fixed_iters=5)
+    c.set_state(st)
+    rest, _ = c.run(steps=2)
+    c.close()
+    # restarting copies psi_{k+1/2} to both levels of the first iterate, so
+    # with a fixed iteration count the restart is compared at its own start
+    want = oracle.Oracle(p).run("oci", steps=2, fixed_iters=5, psi_init=st)["phi"]
+    assert rel(rest, want) <= 1e-12
+    assert rel(full[:2], oracle.Oracle(p).run("oci", steps=2, fixed_iters=5)["phi"]) <= 1e-12
