@@ -15,11 +15,15 @@
 
 namespace oci {
 hipError_t launch_setup(const Slab &S, bool fp32, hipStream_t st);
-hipError_t launch_begin(const Slab &S, bool broadcast_state, hipStream_t st);
+hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, hipStream_t st);
 hipError_t launch_end(const Slab &S, const StepIO &io, hipStream_t st);
 hipError_t launch_oci_step(const Slab &S, const StepIO &io, bool fp32, int np, bool res, int bs, int nwg, int ntiles,
                            hipStream_t st, bool cooperative);
 hipError_t oci_occupancy(bool fp32, int np, bool res, int bs, int *blocks);
+hipError_t local_static_lds(bool fp32, int np, bool res, int bs, size_t *bytes);
+hipError_t local_occupancy(bool fp32, int np, bool res, int bs, size_t dyn, int *blocks);
+hipError_t launch_oci_local(const Slab &S, const StepIO &io, bool fp32, int np, bool res, int bs, int nwg,
+                            int ntiles, size_t dyn, hipStream_t st);
 bool resident_supported(bool fp32, int np);
 bool block_supported(int bs);
 hipError_t launch_si_iteration(const Slab &S, const StepIO &io, hipStream_t st);
@@ -40,6 +44,8 @@ struct oci_handle {
     int nwg, ntiles;       // OCI persistent launch geometry
     int block;             // threads per workgroup of the OCI kernel
     bool resident;
+    bool local;            // workgroup-local kernel (iterate kept in LDS)
+    size_t dyn_lds;        // its dynamic LDS bytes
     bool need_broadcast;   // next step starts from psi_prev on both levels
     int32_t *h_flag;       // pinned host word for SI's convergence polling
     bool profiling;
@@ -130,7 +136,7 @@ static void gauss_legendre(int N, double *mu, double *w) {
 
 // --------------------------------------------------------------- workspace
 struct Layout {
-    size_t ctl, bar, mu, w, dx, st, ss, sp, X, psi0, psi1, phi0, phi1, prev, linv, part, total;
+    size_t ctl, bar, mu, w, dx, st, ss, sp, X, psi0, psi1, phi0, phi1, prev, crhs, exch, linv, part, total;
     int bar_groups;
 };
 
@@ -149,7 +155,7 @@ static Layout layout(const oci_desc *d, int num_cu) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     L.ctl = take(sizeof(Ctl));
-    L.bar_groups = (num_cu * 8 + kBarGroup - 1) / kBarGroup;
+    L.bar_groups = num_cu * 8;  // enough for any arrival-group size >= 1
     L.bar = take((size_t)(2 + L.bar_groups) * kBarStride * 8);
     L.mu = take(N * 8);
     L.w = take(N * 8);
@@ -163,9 +169,11 @@ static Layout layout(const oci_desc *d, int num_cu) {
     L.phi0 = take(J * G * 4 * 8);
     L.phi1 = take(J * G * 4 * 8);
     L.prev = take(J * n / 2 * 8);
+    L.crhs = take(J * n * 8);
+    L.exch = take((size_t)2 * num_cu * 8 * 2 * N * G * 8);
     L.linv = take(J * G * N * 16 * 8);
     const size_t si_blocks = (J * G * 4 + kBlock - 1) / kBlock;
-    size_t parts = (size_t)num_cu * 8;
+    size_t parts = (size_t)num_cu * 8 * 2;
     if (si_blocks > parts) parts = si_blocks;
     L.part = take(parts * 8);
     L.total = o;
@@ -228,11 +236,18 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
     S.phi[0] = (double *)(ws + L.phi0);
     S.phi[1] = (double *)(ws + L.phi1);
     S.psi_prev = (double *)(ws + L.prev);
+    S.crhs = (double *)(ws + L.crhs);
+    S.exch = (double *)(ws + L.exch);
     S.si_linv = (double *)(ws + L.linv);
     S.partials = (double *)(ws + L.part);
     S.ctl = (Ctl *)(ws + L.ctl);
     S.bar = (uint64_t *)(ws + L.bar);
     S.bar_groups = L.bar_groups;
+    S.bar_gsz = kBarGroup;
+    if (const char *env = getenv("OCI_BAR_GROUP")) {
+        const int g = atoi(env);
+        if (g >= 1 && g <= 4096) S.bar_gsz = g;
+    }
     S.tol = desc->tol;
     S.max_iters = desc->max_iters;
     S.fixed_iters = desc->fixed_iters;
@@ -280,12 +295,49 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
         oci_destroy(h);
         return OCI_ERR_HIP;
     }
-    const long wg_cap = (long)num_cu * 8;  // partial-sum slots in the workspace
-    h->resident = false;
+    const long wg_cap = (long)num_cu * 8;  // partial-sum and exchange slots in the workspace
     const char *nores = getenv("OCI_NO_RESIDENT");
-    if (!(nores && atoi(nores)) && resident_supported(h->fp32, h->np) &&
-        oci_occupancy(h->fp32, h->np, true, h->block, &occ_res) == hipSuccess &&
-        (long)occ_res * num_cu >= h->ntiles && h->ntiles <= wg_cap) {
+    const char *mode = getenv("OCI_MODE");
+    const bool allow_res = !(nores && atoi(nores));
+    const bool allow_local = !(mode && strcmp(mode, "global") == 0);
+    h->resident = false;
+    h->local = false;
+    h->dyn_lds = 0;
+    // workgroup-local kernel: the iterate of every owned cell lives in LDS
+    // (dynamic part: cells x (n + 4G) + tiles x 2NG doubles)
+    auto try_local = [&](bool res) -> bool {
+        size_t stat = 0;
+        if (local_static_lds(h->fp32, h->np, res, h->block, &stat) != hipSuccess) return false;
+        const size_t lds_max = 160 * 1024;
+        int occ0 = 0;
+        if (local_occupancy(h->fp32, h->np, res, h->block, 0, &occ0) != hipSuccess || occ0 < 1) return false;
+        long nwg = h->ntiles < (long)occ0 * num_cu ? h->ntiles : (long)occ0 * num_cu;
+        if (nwg > wg_cap) nwg = wg_cap;
+        for (int it = 0; it < 8 && nwg >= 1; ++it) {
+            const long tpw = (h->ntiles + nwg - 1) / nwg;
+            const size_t dyn = ((size_t)tpw * cpt * (h->n + 4 * desc->G) + (size_t)tpw * 2 * desc->N * desc->G) * 8;
+            if (stat + dyn > lds_max) return false;
+            int occ = 0;
+            if (local_occupancy(h->fp32, h->np, res, h->block, dyn, &occ) != hipSuccess || occ < 1) return false;
+            if ((long)occ * num_cu >= nwg) {
+                if (res && nwg != h->ntiles) return false;
+                h->nwg = (int)nwg;
+                h->dyn_lds = dyn;
+                return true;
+            }
+            if (res) return false;
+            nwg = (long)occ * num_cu;
+        }
+        return false;
+    };
+    if (allow_local && allow_res && resident_supported(h->fp32, h->np) && try_local(true)) {
+        h->local = true;
+        h->resident = true;
+    } else if (allow_local && try_local(false)) {
+        h->local = true;
+    } else if (allow_res && resident_supported(h->fp32, h->np) &&
+               oci_occupancy(h->fp32, h->np, true, h->block, &occ_res) == hipSuccess &&
+               (long)occ_res * num_cu >= h->ntiles && h->ntiles <= wg_cap) {
         h->resident = true;
         h->nwg = h->ntiles;
     } else {
@@ -293,6 +345,7 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
         h->nwg = (int)(h->ntiles < cap ? h->ntiles : cap);
     }
     if (h->nwg > wg_cap) h->nwg = (int)wg_cap;
+    S.bar_groups = (h->nwg + S.bar_gsz - 1) / S.bar_gsz;  // counters the barrier uses
     h->need_broadcast = true;
     *out = h;
     return OCI_OK;
@@ -326,11 +379,14 @@ extern "C" int oci_step(oci_handle *h, const double *q_dev, const double *inc_le
     int rc = check_step_args(h, phi_out_dev, info_dev);
     if (rc) return rc;
     StepIO io{q_dev, inc_left_dev, inc_right_dev, phi_out_dev, psi_out_dev, info_dev};
-    HIPCHECK(launch_begin(h->S, h->need_broadcast, h->st));
+    HIPCHECK(launch_begin(h->S, io, h->need_broadcast, h->st));
     h->need_broadcast = false;
     hipEvent_t e0 = h->profiling ? prof_event(h) : nullptr, e1 = h->profiling ? prof_event(h) : nullptr;
     if (e0) HIPCHECK(hipEventRecord(e0, h->st));
-    HIPCHECK(launch_oci_step(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->st, true));
+    if (h->local)
+        HIPCHECK(launch_oci_local(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->dyn_lds, h->st));
+    else
+        HIPCHECK(launch_oci_step(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->st, true));
     if (e1) HIPCHECK(hipEventRecord(e1, h->st));
     HIPCHECK(launch_end(h->S, io, h->st));
     return OCI_OK;
@@ -341,7 +397,7 @@ extern "C" int si_step(oci_handle *h, const double *q_dev, const double *inc_lef
     int rc = check_step_args(h, phi_out_dev, info_dev);
     if (rc) return rc;
     StepIO io{q_dev, inc_left_dev, inc_right_dev, phi_out_dev, psi_out_dev, info_dev};
-    HIPCHECK(launch_begin(h->S, h->need_broadcast, h->st));
+    HIPCHECK(launch_begin(h->S, io, h->need_broadcast, h->st));
     h->need_broadcast = false;
     // the iterations stop themselves on the device; the host only polls the
     // done flag between growing batches of launches

@@ -50,13 +50,16 @@ struct Slab {
     double *psi[2];              // [J][G][N][4] ping-pong iterates
     double *phi[2];              // [J][G][4]   scalar flux of each iterate
     double *psi_prev;            // [J][G][N][2] state psi_{k-1/2}
+    double *crhs;                // [J][G][N][4] constant part of b for the current step
+    double *exch;                // [2][max workgroups][2][2][G][N/2] boundary edges between workgroups
     double *si_linv;             // [J][G][N][16] inverse of the 4x4 SI cell matrix
-    double *partials;            // [max workgroups] per-workgroup sums
+    double *partials;            // [2][max workgroups] per-workgroup sums (iteration parity)
     Ctl *ctl;
     // grid barrier words, 256 bytes apart: [0] arrivals of group leaders,
     // [kBarStride] release flag, [(2 + k) * kBarStride] arrivals in group k
     uint64_t *bar;
     int32_t bar_groups;          // group counters present in `bar`
+    int32_t bar_gsz;             // workgroups per arrival group
     // step controls
     double tol;
     int32_t max_iters, fixed_iters, norm, refined;

@@ -164,65 +164,80 @@ __device__ inline double block_sum_t(double v, double *s_tmp) {
     return t;  // valid in thread 0
 }
 
-// Grid barrier over the co-resident workgroups of one launch, used once per
-// iteration (index l).  Counters only grow during a step (reset before it),
-// so a workgroup knows the target of barrier l without reading shared state:
-// workgroups arrive at their group's counter; the last of a group arrives at
-// the top counter; the last of all runs `last()` (the reduction and the
-// stopping decision) and then raises the release flag to l + 1.  Each
-// workgroup publishes its stores with one agent-scope release (its arrival)
-// and waits with relaxed loads followed by one agent-scope acquire, so no
-// cache maintenance happens inside the spin.  The spin is bounded: on expiry
-// the control block's err flag is raised and every workgroup leaves its loop.
+// Grid barrier over the co-resident workgroups of one launch, once per
+// iteration l, fused with the reduction of the per-workgroup sums.
+// Counters only grow during a step (they are reset before it), so barrier l
+// has a known target and nobody reads shared state to learn it: workgroups
+// arrive at their group's counter, the last of a group arrives at the top
+// counter, and everybody waits for the top counter to reach (l + 1) x groups.
+// Arrivals are agent-scope acquire-release read-modify-writes (publishing the
+// workgroup's stores, its partial sum included); the wait uses relaxed loads
+// and one agent-scope acquire at the end, so no cache maintenance happens
+// inside the spin.  Then every workgroup sums the partials of iteration l in
+// the same fixed order, so all of them hold the identical total and take the
+// identical stopping decision with no second round trip.  The spin is
+// bounded: on expiry the control block's err flag is raised and the caller
+// leaves its loop, so the grid always drains.
 constexpr long kSpinLimit = 1L << 25;
 
-template <typename F>
-__device__ inline bool grid_barrier(const Slab &S, unsigned nwg, int l, int *s_flag, F last) {
+template <int BS>
+__device__ inline bool grid_sync_sum(const Slab &S, unsigned nwg, int l, double wg_sum, int *s_flag,
+                                     double *s_tmp, double *total) {
+    double *part = S.partials + (size_t)(l & 1) * nwg;
+    if (threadIdx.x == 0) part[blockIdx.x] = wg_sum;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned wg = blockIdx.x;
-        const unsigned grp = wg / kBarGroup;
-        const unsigned ngrp = (nwg + kBarGroup - 1) / kBarGroup;
-        const unsigned gsz = (grp + 1 == ngrp) ? nwg - grp * kBarGroup : kBarGroup;
+        const unsigned gsz_all = (unsigned)S.bar_gsz;
+        const unsigned grp = blockIdx.x / gsz_all;
+        const unsigned ngrp = (nwg + gsz_all - 1) / gsz_all;
+        const unsigned gsz = (grp + 1 == ngrp) ? nwg - grp * gsz_all : gsz_all;
         const uint64_t round = (uint64_t)l + 1;
         uint64_t *gc = S.bar + (size_t)(2 + grp) * kBarStride;
         const uint64_t og = __hip_atomic_fetch_add(gc, (uint64_t)1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        int is_last = 0;
-        if (og + 1 == round * gsz) {
-            const uint64_t ot = __hip_atomic_fetch_add(S.bar, (uint64_t)1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            is_last = (ot + 1 == round * ngrp);
-        }
-        s_flag[0] = is_last;
-        s_flag[2] = 0;
-    }
-    __syncthreads();
-    if (s_flag[0]) {
-        last();
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_store(S.bar + kBarStride, (uint64_t)l + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else if (threadIdx.x == 0) {
+        if (og + 1 == round * gsz)
+            (void)__hip_atomic_fetch_add(S.bar, (uint64_t)1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        int bad = 0;
         long spins = 0;
-        while (__hip_atomic_load(S.bar + kBarStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint64_t)l + 1) {
+        while (__hip_atomic_load(S.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round * ngrp) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > kSpinLimit) {
                 __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_flag[2] = 1;
+                bad = 1;
                 break;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (__hip_atomic_load(&S.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) s_flag[2] = 1;
+        s_flag[2] = bad;
     }
     __syncthreads();
+    double v = 0.0;
+    for (unsigned k = threadIdx.x; k < nwg; k += BS) v += part[k];
+    v = block_sum_t<BS>(v, s_tmp);
+    if (threadIdx.x == 0) s_tmp[BS / 64] = v;
+    __syncthreads();
+    *total = s_tmp[BS / 64];
     return s_flag[2] == 0;
+}
+
+// Coefficients of row u of the 4x4 corner block L_{c,j,g,m} (eq. Aj) acting
+// on (psi_kL, psi_kR, psi_hL, psi_hR) of the same (g, m).
+__device__ inline void lc_row(const Slab &S, int j, int g, double mu, int u, double c[4]) {
+    const double dx = S.dx[j];
+    const double a = dx / (S.speed[g] * S.dt);
+    const double d = 0.5 * (fabs(mu) + dx * S.sigma_t[(size_t)j * S.G + g]);
+    const double h = 0.5 * mu;
+    if (u == 0) { c[0] = d; c[1] = h; c[2] = 0.5 * a; c[3] = 0.0; }
+    else if (u == 1) { c[0] = -h; c[1] = d; c[2] = 0.0; c[3] = 0.5 * a; }
+    else if (u == 2) { c[0] = -a; c[1] = 0.0; c[2] = a + d; c[3] = h; }
+    else { c[0] = 0.0; c[1] = -a; c[2] = -h; c[3] = a + d; }
 }
 
 // The persistent OCI kernel.  T = float: refined path (FP32 inverse applied
 // to the power-of-two scaled FP64 residual); T = double: plain FP64 path.
 // NP: padded cell size (power of two >= n); RES: each thread keeps its row of
-// the inverse in registers for the whole step (one tile per workgroup);
-// BS: threads per workgroup.  At most 128 VGPRs (4 waves per SIMD).
+// the inverse in registers, and the row's constants in LDS, for the whole
+// step (one tile per workgroup); BS: threads per workgroup.  At most 128
+// VGPRs (4 waves per SIMD).
 template <typename T, int NP, bool RES, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
 void k_oci_step(Slab S, StepIO io, int ntiles) {
@@ -232,12 +247,16 @@ void k_oci_step(Slab S, StepIO io, int ntiles) {
     constexpr int CPT = BS / TPC;                 // cells per tile
     constexpr int V = 16 / sizeof(T);
     constexpr int NV = NP / V;
+    constexpr bool CACHE = RES && REF;            // row constants cached in LDS
     typedef typename Vec16<T>::type VT;
 
     __shared__ __align__(16) T s_vec[CPT][NP];
     __shared__ double s_psi[REF ? CPT : 1][REF ? NP : 1];
     __shared__ double s_wx[CPT][NP];
     __shared__ double s_phi[REF ? CPT : 1][REF ? NP / 2 : 1];
+    __shared__ double s_coef[CACHE ? CPT : 1][CACHE ? NP : 1][4];
+    __shared__ double s_crow[CACHE ? CPT : 1][CACHE ? NP : 1];
+    __shared__ double s_scat[CACHE ? CPT : 1][CACHE ? NP / 8 * NP / 8 : 1];
     __shared__ double s_mu[NP / 4], s_w[NP / 4];
     __shared__ double s_tmp[BS / 64 + 1];
     __shared__ double s_max[BS / 64];
@@ -265,7 +284,20 @@ void k_oci_step(Slab S, StepIO io, int ntiles) {
         }
     }
     __syncthreads();
+    if constexpr (CACHE) {
+        const int j = tile0 * CPT + cl;
+        const int i = t;
+        if (tile0 < tile1 && j < J && i < n) {
+            const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
+            lc_row(S, j, g, s_mu[m], u, s_coef[cl][i]);
+            s_crow[cl][i] = S.crhs[(size_t)j * n + i];
+        }
+        if (tile0 < tile1 && j < J && t < G * G)
+            s_scat[cl][t] = 0.25 * S.dx[j] * S.sigma_s[(size_t)j * G * G + t];
+        __syncthreads();
+    }
 
+    double e_prev = __builtin_nan("");
     const int base = S.ctl->base;
     for (int l = 0;; ++l) {
         const int cur = (base + l) & 1;
@@ -281,8 +313,7 @@ void k_oci_step(Slab S, StepIO io, int ntiles) {
             double xold[RPT];
             int expo = 0;
 
-            // (1) b (eq. rhs_sg) with the lagged incident edge; refined: the
-            //     own iterate and its scalar flux into LDS for the residual
+            // (1) b = constant part (per step) + lagged incident edge (eq. rhs_sg)
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 const int i = t + r * TPC;
@@ -290,12 +321,9 @@ void k_oci_step(Slab S, StepIO io, int ntiles) {
                 xold[r] = 0.0;
                 if (live && i < n) {
                     const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
-                    const double dx = S.dx[j];
                     const double mu = s_mu[m];
-                    const size_t jg = (size_t)j * G + g;
                     xold[r] = psi_in[(size_t)j * n + i];
-                    if (io.q) b = 0.25 * dx * io.q[jg * 4 + u];
-                    if (u < 2) b += dx / (2.0 * S.speed[g] * S.dt) * S.psi_prev[(jg * N + m) * 2 + u];
+                    b = CACHE ? s_crow[cl][i] : S.crhs[(size_t)j * n + i];
                     if (mu > 0.0 && !(u & 1)) {
                         const double e = j > 0 ? psi_in[(((size_t)(j - 1) * G + g) * N + m) * 4 + u + 1]
                                                : (io.inc_l ? io.inc_l[((size_t)(u >> 1) * G + g) * (N / 2) + (m - N / 2)] : 0.0);
@@ -316,7 +344,8 @@ void k_oci_step(Slab S, StepIO io, int ntiles) {
             if constexpr (REF) {
                 if (live && t < 4 * G) s_phi[cl][t] = phi_in[(size_t)j * 4 * G + t];
                 __syncthreads();
-                // (2) FP64 residual r = b - A_j Psi^(l), matrix-free
+                // (2) FP64 residual r = b - A_j Psi^(l), matrix-free:
+                //     L_c rows on the corner quad, scattering through phi
                 double rr[RPT];
                 double mx = 0.0;
 #pragma unroll
@@ -324,22 +353,25 @@ void k_oci_step(Slab S, StepIO io, int ntiles) {
                     const int i = t + r * TPC;
                     double res = 0.0;
                     if (live && i < n) {
-                        const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
-                        const double dx = S.dx[j];
-                        const double mu = s_mu[m];
-                        const size_t jg = (size_t)j * G + g;
-                        const double a = dx / (S.speed[g] * S.dt);
-                        const double d = 0.5 * (fabs(mu) + dx * S.sigma_t[jg]);
-                        const double h = 0.5 * mu;
+                        const int g = i / (4 * N), u = i & 3;
+                        double cf[4];
+                        if constexpr (CACHE) {
+                            cf[0] = s_coef[cl][i][0]; cf[1] = s_coef[cl][i][1];
+                            cf[2] = s_coef[cl][i][2]; cf[3] = s_coef[cl][i][3];
+                        } else {
+                            lc_row(S, j, g, s_mu[(i >> 2) % N], u, cf);
+                        }
                         const double *p = &s_psi[cl][i & ~3];
-                        double lp;
-                        if (u == 0) lp = d * p[0] + h * p[1] + 0.5 * a * p[2];
-                        else if (u == 1) lp = -h * p[0] + d * p[1] + 0.5 * a * p[3];
-                        else if (u == 2) lp = -a * p[0] + (a + d) * p[2] + h * p[3];
-                        else lp = -a * p[1] - h * p[2] + (a + d) * p[3];
+                        const double lp = cf[0] * p[0] + cf[1] * p[1] + cf[2] * p[2] + cf[3] * p[3];
                         double sc = 0.0;
-                        for (int gp = 0; gp < G; ++gp) sc += S.sigma_s[jg * G + gp] * s_phi[cl][gp * 4 + u];
-                        res = s_wx[cl][i] - lp + 0.25 * dx * sc;
+                        if constexpr (CACHE) {
+                            for (int gp = 0; gp < G; ++gp) sc += s_scat[cl][g * G + gp] * s_phi[cl][gp * 4 + u];
+                        } else {
+                            const double *ss = S.sigma_s + ((size_t)j * G + g) * G;
+                            for (int gp = 0; gp < G; ++gp) sc += ss[gp] * s_phi[cl][gp * 4 + u];
+                            sc *= 0.25 * S.dx[j];
+                        }
+                        res = s_wx[cl][i] - lp + sc;
                     }
                     rr[r] = res;
                     mx = fmax(mx, fabs(res));
@@ -414,20 +446,424 @@ void k_oci_step(Slab S, StepIO io, int ntiles) {
             const double part = block_sum_t<BS>(dsq, s_tmp);
             if (tid == 0) wg_sum += part;
         }
-        if (tid == 0) S.partials[wg] = wg_sum;
 
-        // (5) grid barrier; the last workgroup reduces and decides
-        const bool ok = grid_barrier(S, nwg, l, s_flag, [&]() {
-            double v = 0.0;
-            for (unsigned k = tid; k < nwg; k += BS) v += S.partials[k];
-            const double tot = block_sum_t<BS>(v, s_tmp);
-            if (tid == 0) decide(S, sqrt(tot));
-        });
+        // (5) grid barrier + reduction; every workgroup decides identically
+        double tot = 0.0;
+        const bool ok = grid_sync_sum<BS>(S, nwg, l, wg_sum, s_flag, s_tmp, &tot);
         if (!ok) break;
-        if (tid == 0) s_flag[3] = __hip_atomic_load(&S.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        if (s_flag[3]) break;
+        const int iters = l + 1;
+        const double e = sqrt(tot);
+        const double rho = iters >= 2 ? e / e_prev : __builtin_nan("");
+        int done = 0, status = OK;
+        if (!isfinite(e)) { done = 1; status = NONFINITE; }
+        else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
+        else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - e / e_prev))) done = 1;
+        else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
+        e_prev = e;
+        if (done) {
+            if (wg == 0 && tid == 0) {
+                Ctl *c = S.ctl;
+                c->iter = iters;
+                c->e_last = e;
+                c->rho = rho;
+                c->e_prev = e;
+                c->status = status;
+                c->done = 1;
+            }
+            break;
+        }
     }
+}
+
+// Relaxed agent-scope accesses: coherent across the XCDs without any L2
+// writeback or invalidate.  Only the data that crosses workgroups inside a
+// launch (boundary edges, partial sums, barrier counters) goes through them.
+__device__ inline void st_agent(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_agent(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier for the workgroup-local kernel: every wave first waits for its
+// own agent-scope stores to complete (s_waitcnt), so when the counters reach
+// their target every published value is at the coherence point; arrivals and
+// the wait are relaxed, and no cache maintenance is issued.  Then each
+// workgroup sums the published partials of iteration l in a fixed order.
+template <int BS>
+__device__ inline bool grid_sync_local(const Slab &S, unsigned nwg, int l, double wg_sum, int *s_flag,
+                                       double *s_tmp, double *total) {
+    double *part = S.partials + (size_t)(l & 1) * nwg;
+    if (threadIdx.x == 0) st_agent(part + blockIdx.x, wg_sum);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned gsz_all = (unsigned)S.bar_gsz;
+        const unsigned grp = blockIdx.x / gsz_all;
+        const unsigned ngrp = (nwg + gsz_all - 1) / gsz_all;
+        const unsigned gsz = (grp + 1 == ngrp) ? nwg - grp * gsz_all : gsz_all;
+        const uint64_t round = (uint64_t)l + 1;
+        uint64_t *gc = S.bar + (size_t)(2 + grp) * kBarStride;
+        const uint64_t og = __hip_atomic_fetch_add(gc, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (og + 1 == round * gsz) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            (void)__hip_atomic_fetch_add(S.bar, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        int bad = 0;
+        long spins = 0;
+        while (__hip_atomic_load(S.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round * ngrp) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+                __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                bad = 1;
+                break;
+            }
+        }
+        asm volatile("" ::: "memory");
+        s_flag[2] = bad;
+    }
+    __syncthreads();
+    double v = 0.0;
+    for (unsigned k = threadIdx.x; k < nwg; k += BS) v += ld_agent(part + k);
+    v = block_sum_t<BS>(v, s_tmp);
+    if (threadIdx.x == 0) s_tmp[BS / 64] = v;
+    __syncthreads();
+    *total = s_tmp[BS / 64];
+    return s_flag[2] == 0;
+}
+
+// Workgroup-local persistent OCI kernel.  Each workgroup owns the contiguous
+// cells [c0, c1) for the whole step and keeps their iterate Psi and scalar
+// flux phi in LDS (dynamic shared memory: [cells][n] Psi, [cells][4G] phi,
+// then per internal tile boundary a snapshot of the 2NG edge values that
+// cross it).  Only the edges at the two ends of the range cross workgroups:
+// they are published each iteration into the exchange buffer with agent-scope
+// stores and read by the neighbour with agent-scope loads after the barrier.
+// Iterate 0's neighbour edges come from global memory (written by earlier
+// launches).  At the end the final Psi and phi are written to global memory.
+// Template parameters as k_oci_step.
+template <typename T, int NP, bool RES, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
+void k_oci_local(Slab S, StepIO io, int ntiles) {
+    constexpr bool REF = sizeof(T) == 4;
+    constexpr int RPT = NP > BS ? NP / BS : 1;
+    constexpr int TPC = NP / RPT;
+    constexpr int CPT = BS / TPC;
+    constexpr int V = 16 / sizeof(T);
+    constexpr int NV = NP / V;
+    constexpr bool CACHE = RES && REF;
+    typedef typename Vec16<T>::type VT;
+
+    extern __shared__ __align__(16) double s_dyn[];
+    __shared__ __align__(16) T s_vec[CPT][NP];
+    __shared__ double s_wx[CPT][NP];
+    __shared__ double s_coef[CACHE ? CPT : 1][CACHE ? NP : 1][4];
+    __shared__ double s_crow[CACHE ? CPT : 1][CACHE ? NP : 1];
+    __shared__ double s_scat[CACHE ? CPT : 1][CACHE ? NP / 8 * NP / 8 : 1];
+    __shared__ double s_mu[NP / 4], s_w[NP / 4];
+    __shared__ double s_tmp[BS / 64 + 1];
+    __shared__ double s_max[BS / 64];
+    __shared__ int s_flag[4];
+
+    const int tid = threadIdx.x;
+    const int cl = tid / TPC;
+    const int t = tid % TPC;
+    const int J = S.J, N = S.N, G = S.G, n = S.n, nh = S.N / 2, NG = S.N * S.G;
+    const unsigned nwg = gridDim.x;
+    const int wg = blockIdx.x;
+    const int tile0 = (int)(((long)ntiles * wg) / nwg);
+    const int tile1 = (int)(((long)ntiles * (wg + 1)) / nwg);
+    const int ntw = tile1 - tile0;
+    const int c0 = tile0 * CPT;
+    const int c1 = min(tile1 * CPT, J);
+    const int ncell = ntw * CPT;
+    double *L_psi = s_dyn;                                   // [ncell][n]
+    double *L_phi = L_psi + (size_t)ncell * n;               // [ncell][4G]
+    double *L_snap = L_phi + (size_t)ncell * 4 * G;          // [ntw][2][NG]: R-going, L-going
+    // exchange buffer [2 parity][nwg][2 side][2 lev][G][nh]; side 0: my first
+    // cell's L corners of mu<0 angles, side 1: my last cell's R corners of mu>0
+    const size_t exw = (size_t)2 * 2 * G * nh;
+    auto exq = [&](int par, int w, int side, int lev, int g, int mm) -> double * {
+        return S.exch + (((size_t)par * nwg + w) * 2 + side) * (exw / 2) + ((size_t)lev * G + g) * nh + mm;
+    };
+
+    for (int m = tid; m < N; m += BS) { s_mu[m] = S.mu[m]; s_w[m] = S.w[m]; }
+
+    const T *Xall = reinterpret_cast<const T *>(S.X);
+    VT xr[RES ? NV : 1];
+    if constexpr (RES) {
+        const int j = tile0 * CPT + cl;
+        if (ntw > 0 && j < J) {
+            const T *Xc = Xall + (size_t)j * NP * NP;
+#pragma unroll
+            for (int kv = 0; kv < NV; ++kv) xr[kv] = *reinterpret_cast<const VT *>(Xc + ((size_t)kv * NP + t) * V);
+        }
+    }
+    // the iterate and its scalar flux into LDS
+    const int base = S.ctl->base;
+    {
+        const double *pin = S.psi[base] + (size_t)c0 * n;
+        const int tot = (c1 - c0) * n;
+        for (int k = tid; k < tot; k += BS) L_psi[k] = pin[k];
+        const double *fin = S.phi[base] + (size_t)c0 * 4 * G;
+        const int totf = (c1 - c0) * 4 * G;
+        for (int k = tid; k < totf; k += BS) L_phi[k] = fin[k];
+    }
+    __syncthreads();
+    if constexpr (CACHE) {
+        const int j = tile0 * CPT + cl;
+        const int i = t;
+        if (ntw > 0 && j < J && i < n) {
+            const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
+            lc_row(S, j, g, s_mu[m], u, s_coef[cl][i]);
+            s_crow[cl][i] = S.crhs[(size_t)j * n + i];
+        }
+        if (ntw > 0 && j < J && t < G * G) s_scat[cl][t] = 0.25 * S.dx[j] * S.sigma_s[(size_t)j * G * G + t];
+        __syncthreads();
+    }
+
+    double e_prev = __builtin_nan("");
+    for (int l = 0;; ++l) {
+        const int cur = (base + l) & 1;
+        const double *__restrict__ psi_g = S.psi[cur];   // global iterate: only read at l = 0
+        double wg_sum = 0.0;
+
+        // edges crossing internal tile boundaries, before any tile updates
+        for (int k = tid; k < (ntw - 1) * 2 * NG; k += BS) {
+            const int tt = 1 + k / (2 * NG), r = k % (2 * NG);
+            const int side = r / NG, q = r % NG;           // side 0: R-going, 1: L-going
+            const int lev = q / (G * nh), g = (q / nh) % G, mm = q % nh;
+            const int jb = (tile0 + tt) * CPT;             // first cell of tile tt
+            double v;
+            if (side == 0) v = L_psi[(size_t)(jb - 1 - c0) * n + (g * N + nh + mm) * 4 + 2 * lev + 1];
+            else v = L_psi[(size_t)(jb - c0) * n + (g * N + mm) * 4 + 2 * lev];
+            L_snap[(size_t)tt * 2 * NG + r] = v;
+        }
+        __syncthreads();
+
+        for (int tile = tile0; tile < tile1; ++tile) {
+            const int tt = tile - tile0;
+            const int j = tile * CPT + cl;
+            const bool live = j < J;
+            double *Lp = L_psi + (size_t)(j - c0) * n;          // this cell's iterate
+            double *Lf = L_phi + (size_t)(j - c0) * 4 * G;
+            double xold[RPT];
+            int expo = 0;
+
+            // (1) b = constant part + lagged incident edge
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int i = t + r * TPC;
+                double b = 0.0;
+                xold[r] = 0.0;
+                if (live && i < n) {
+                    const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
+                    const double mu = s_mu[m];
+                    xold[r] = Lp[i];
+                    b = CACHE ? s_crow[cl][i] : S.crhs[(size_t)j * n + i];
+                    const int lev = u >> 1;
+                    if (mu > 0.0 && !(u & 1)) {
+                        double e;
+                        if (j == 0)
+                            e = io.inc_l ? io.inc_l[((size_t)lev * G + g) * nh + (m - nh)] : 0.0;
+                        else if (j % CPT != 0)
+                            e = Lp[i - n + 1];                                   // same tile
+                        else if (j - 1 >= c0)
+                            e = L_snap[(size_t)tt * 2 * NG + (lev * G + g) * nh + (m - nh)];
+                        else if (l == 0)
+                            e = psi_g[(size_t)(j - 1) * n + i + 1];
+                        else
+                            e = ld_agent(exq(l & 1, wg - 1, 1, lev, g, m - nh));
+                        b += mu * e;
+                    } else if (mu < 0.0 && (u & 1)) {
+                        double e;
+                        if (j == J - 1)
+                            e = io.inc_r ? io.inc_r[((size_t)lev * G + g) * nh + m] : 0.0;
+                        else if ((j + 1) % CPT != 0)
+                            e = Lp[i + n - 1];                                   // same tile
+                        else if (j + 1 < c1)
+                            e = L_snap[(size_t)(tt + 1) * 2 * NG + NG + (lev * G + g) * nh + m];
+                        else if (l == 0)
+                            e = psi_g[(size_t)(j + 1) * n + i - 1];
+                        else
+                            e = ld_agent(exq(l & 1, wg + 1, 0, lev, g, m));
+                        b -= mu * e;
+                    }
+                }
+                if constexpr (REF) s_wx[cl][i] = b;
+                else s_vec[cl][i] = b;
+            }
+            if constexpr (REF) {
+                __syncthreads();
+                // (2) FP64 residual r = b - A_j Psi^(l), matrix-free
+                double rr[RPT];
+                double mx = 0.0;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const int i = t + r * TPC;
+                    double res = 0.0;
+                    if (live && i < n) {
+                        const int g = i / (4 * N), u = i & 3;
+                        double cf[4];
+                        if constexpr (CACHE) {
+                            cf[0] = s_coef[cl][i][0]; cf[1] = s_coef[cl][i][1];
+                            cf[2] = s_coef[cl][i][2]; cf[3] = s_coef[cl][i][3];
+                        } else {
+                            lc_row(S, j, g, s_mu[(i >> 2) % N], u, cf);
+                        }
+                        const double *p = Lp + (i & ~3);
+                        const double lp = cf[0] * p[0] + cf[1] * p[1] + cf[2] * p[2] + cf[3] * p[3];
+                        double sc = 0.0;
+                        if constexpr (CACHE) {
+                            for (int gp = 0; gp < G; ++gp) sc += s_scat[cl][g * G + gp] * Lf[gp * 4 + u];
+                        } else {
+                            const double *ss = S.sigma_s + ((size_t)j * G + g) * G;
+                            for (int gp = 0; gp < G; ++gp) sc += ss[gp] * Lf[gp * 4 + u];
+                            sc *= 0.25 * S.dx[j];
+                        }
+                        res = s_wx[cl][i] - lp + sc;
+                    }
+                    rr[r] = res;
+                    mx = fmax(mx, fabs(res));
+                }
+                if constexpr (TPC <= 64) {
+#pragma unroll
+                    for (int off = TPC / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+                } else {
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+                    if ((tid & 63) == 0) s_max[tid >> 6] = mx;
+                    __syncthreads();
+                    mx = 0.0;
+                    for (int w = cl * (TPC / 64); w < (cl + 1) * (TPC / 64); ++w) mx = fmax(mx, s_max[w]);
+                }
+                if (mx > 0.0 && isfinite(mx)) frexp(mx, &expo);
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) s_vec[cl][t + r * TPC] = (T)ldexp(rr[r], -expo);
+            }
+            __syncthreads();
+
+            // (3) apply the inverse, one row per thread
+            T acc[RPT];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) acc[r] = T(0);
+            if (live) {
+                if constexpr (RES) {
+#pragma unroll
+                    for (int kv = 0; kv < NV; ++kv) {
+                        const VT bv = *reinterpret_cast<const VT *>(&s_vec[cl][kv * V]);
+                        acc[0] += dot16(xr[kv], bv);
+                    }
+                } else {
+                    const T *Xc = Xall + (size_t)j * NP * NP;
+#pragma unroll 8
+                    for (int kv = 0; kv < NV; ++kv) {
+                        const VT bv = *reinterpret_cast<const VT *>(&s_vec[cl][kv * V]);
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) {
+                            const VT xv = *reinterpret_cast<const VT *>(Xc + ((size_t)kv * NP + t + r * TPC) * V);
+                            acc[r] += dot16(xv, bv);
+                        }
+                    }
+                }
+            }
+            __syncthreads();   // every read of this tile's Psi^(l) is done
+
+            // (4) new iterate into LDS, scalar flux and its change
+            double dsq = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int i = t + r * TPC;
+                double x = REF ? xold[r] + ldexp((double)acc[r], expo) : (double)acc[r];
+                if (live && i < n) {
+                    Lp[i] = x;
+                    if (S.norm == 1) dsq += (x - xold[r]) * (x - xold[r]);
+                } else {
+                    x = 0.0;
+                }
+                s_wx[cl][i] = (i < n ? s_w[(i >> 2) % N] : 0.0) * x;
+            }
+            __syncthreads();
+            if (live && t < 4 * G) {
+                const int g = t >> 2, u = t & 3;
+                double f = 0.0;
+                for (int m = 0; m < N; ++m) f += s_wx[cl][(g * N + m) * 4 + u];
+                const double f0 = Lf[t];
+                Lf[t] = f;
+                if (S.norm == 0) dsq += (f - f0) * (f - f0);
+            }
+            const double part = block_sum_t<BS>(dsq, s_tmp);
+            if (tid == 0) wg_sum += part;
+        }
+
+        // (5) publish the two end edges of the range for iteration l + 1
+        {
+            const int par = (l + 1) & 1;
+            for (int k = tid; k < 2 * NG; k += BS) {
+                const int side = k / NG, q = k % NG;
+                const int lev = q / (G * nh), g = (q / nh) % G, mm = q % nh;
+                if (side == 0 && wg > 0 && c1 > c0)
+                    st_agent(exq(par, wg, 0, lev, g, mm), L_psi[(g * N + mm) * 4 + 2 * lev]);
+                if (side == 1 && wg + 1 < (int)nwg && c1 > c0)
+                    st_agent(exq(par, wg, 1, lev, g, mm),
+                             L_psi[(size_t)(c1 - 1 - c0) * n + (g * N + nh + mm) * 4 + 2 * lev + 1]);
+            }
+        }
+
+        // (6) barrier + reduction; every workgroup decides identically
+        double tot = 0.0;
+        const bool ok = grid_sync_local<BS>(S, nwg, l, wg_sum, s_flag, s_tmp, &tot);
+        const int iters = l + 1;
+        const double e = sqrt(tot);
+        const double rho = iters >= 2 ? e / e_prev : __builtin_nan("");
+        int done = 0, status = OK;
+        if (!ok) done = 1;
+        else if (!isfinite(e)) { done = 1; status = NONFINITE; }
+        else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
+        else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - e / e_prev))) done = 1;
+        else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
+        e_prev = e;
+        if (done) {
+            // the final iterate and its flux leave LDS
+            const int fin = (base + iters) & 1;
+            double *pout = S.psi[fin] + (size_t)c0 * n;
+            const int totp = (c1 - c0) * n;
+            for (int k = tid; k < totp; k += BS) pout[k] = L_psi[k];
+            double *fout = S.phi[fin] + (size_t)c0 * 4 * G;
+            const int totf = (c1 - c0) * 4 * G;
+            for (int k = tid; k < totf; k += BS) fout[k] = L_phi[k];
+            if (wg == 0 && tid == 0) {
+                Ctl *c = S.ctl;
+                c->iter = iters;
+                c->e_last = e;
+                c->rho = rho;
+                c->e_prev = e;
+                c->status = status;
+                c->done = 1;
+            }
+            break;
+        }
+    }
+}
+
+// Constant part of b for the current step (eq. rhs_sg without the incident
+// terms): dx/4 Q_u, plus dx/(2 v dt) psi_{k-1/2} in the level-k rows.  One
+// thread per row of every cell; used by every iteration of OCI and SI.
+__global__ __launch_bounds__(kBlock) void k_const_rhs(Slab S, StepIO io) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const size_t total = (size_t)S.J * S.n;
+    if (t >= total) return;
+    const int u = t & 3;
+    const size_t jgm = t >> 2;
+    const int m = jgm % S.N;
+    const size_t jg = jgm / S.N;
+    const int g = jg % S.G;
+    const int j = jg / S.G;
+    const double dx = S.dx[j];
+    double c = io.q ? 0.25 * dx * io.q[jg * 4 + u] : 0.0;
+    if (u < 2) c += dx / (2.0 * S.speed[g] * S.dt) * S.psi_prev[jgm * 2 + u];
+    (void)m;
+    S.crhs[t] = c;
 }
 
 // --------------------------------------------------------------- SI kernels
@@ -452,19 +888,17 @@ __global__ __launch_bounds__(64) void k_si_sweep(Slab S, StepIO io) {
         e0 = io.inc_r ? io.inc_r[(size_t)g * (N / 2) + m] : 0.0;
         e1 = io.inc_r ? io.inc_r[((size_t)G + g) * (N / 2) + m] : 0.0;
     }
-    const double a2c = 1.0 / (2.0 * S.speed[g] * S.dt);
     for (int s = 0; s < J; ++s) {
         const int j = pos ? s : J - 1 - s;
         const size_t jg = (size_t)j * G + g;
         const double dx = S.dx[j];
+        const double *cr = S.crhs + (jg * N + m) * 4;
         double d[4];
         for (int u = 0; u < 4; ++u) {
             double sc = 0.0;
             for (int gp = 0; gp < G; ++gp) sc += S.sigma_s[jg * G + gp] * phi_in[((size_t)j * G + gp) * 4 + u];
-            d[u] = 0.25 * dx * ((io.q ? io.q[jg * 4 + u] : 0.0) + sc);
+            d[u] = cr[u] + 0.25 * dx * sc;
         }
-        d[0] += dx * a2c * S.psi_prev[(jg * N + m) * 2 + 0];
-        d[1] += dx * a2c * S.psi_prev[(jg * N + m) * 2 + 1];
         if (pos) { d[0] += mu * e0; d[2] += mu * e1; }
         else { d[1] -= mu * e0; d[3] -= mu * e1; }
         const double *Li = S.si_linv + (jg * N + m) * 16;
@@ -562,6 +996,50 @@ static hipError_t dispatch(bool fp32, int np, bool res, int bs, F f) {
     return bs == 1024 ? by_np<double, false, 1024>(np, f) : by_np<double, false, 256>(np, f);
 }
 
+template <typename T, int NP, bool RES, int BS>
+static hipError_t launch_local_t(const Slab &S, const StepIO &io, int nwg, int ntiles, size_t dyn, hipStream_t st) {
+    const void *f = (const void *)&k_oci_local<T, NP, RES, BS>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+    void *args[] = {(void *)&S, (void *)&io, (void *)&ntiles};
+    return hipLaunchCooperativeKernel(f, dim3(nwg), dim3(BS), args, (unsigned)dyn, st);
+}
+
+template <typename T, int NP, bool RES, int BS>
+static hipError_t occupancy_local_t(int *blocks, size_t dyn) {
+    const void *f = (const void *)&k_oci_local<T, NP, RES, BS>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, BS, dyn);
+}
+
+template <typename T, int NP, bool RES, int BS>
+static size_t static_lds_local_t() {
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, (const void *)&k_oci_local<T, NP, RES, BS>) != hipSuccess) return (size_t)-1;
+    return a.sharedSizeBytes;
+}
+
+struct OccLocalF {
+    int *blocks; size_t dyn;
+    template <typename T, int NP, bool RES, int BS> hipError_t operator()() {
+        return occupancy_local_t<T, NP, RES, BS>(blocks, dyn);
+    }
+};
+struct StaticLdsF {
+    size_t *bytes;
+    template <typename T, int NP, bool RES, int BS> hipError_t operator()() {
+        *bytes = static_lds_local_t<T, NP, RES, BS>();
+        return *bytes == (size_t)-1 ? hipErrorInvalidValue : hipSuccess;
+    }
+};
+struct LaunchLocalF {
+    const Slab &S; const StepIO &io; int nwg, ntiles; size_t dyn; hipStream_t st;
+    template <typename T, int NP, bool RES, int BS> hipError_t operator()() {
+        return launch_local_t<T, NP, RES, BS>(S, io, nwg, ntiles, dyn, st);
+    }
+};
+
 struct OccF {
     int *blocks;
     template <typename T, int NP, bool RES, int BS> hipError_t operator()() { return occupancy_t<T, NP, RES, BS>(blocks); }
@@ -582,8 +1060,25 @@ hipError_t launch_oci_step(const Slab &S, const StepIO &io, bool fp32, int np, b
     return dispatch(fp32, np, res, bs, LaunchF{S, io, nwg, ntiles, st, cooperative});
 }
 
-hipError_t launch_begin(const Slab &S, bool broadcast_state, hipStream_t st) {
+hipError_t local_static_lds(bool fp32, int np, bool res, int bs, size_t *bytes) {
+    return dispatch(fp32, np, res, bs, StaticLdsF{bytes});
+}
+
+hipError_t local_occupancy(bool fp32, int np, bool res, int bs, size_t dyn, int *blocks) {
+    return dispatch(fp32, np, res, bs, OccLocalF{blocks, dyn});
+}
+
+hipError_t launch_oci_local(const Slab &S, const StepIO &io, bool fp32, int np, bool res, int bs, int nwg,
+                            int ntiles, size_t dyn, hipStream_t st) {
+    return dispatch(fp32, np, res, bs, LaunchLocalF{S, io, nwg, ntiles, dyn, st});
+}
+
+hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, hipStream_t st) {
     hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, st, S);
+    {
+        const size_t tot = (size_t)S.J * S.n;
+        hipLaunchKernelGGL(k_const_rhs, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S, io);
+    }
     if (broadcast_state) {
         const size_t tot = (size_t)S.J * S.G * S.N * 4;
         hipLaunchKernelGGL(k_broadcast_state, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S);

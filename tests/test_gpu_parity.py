@@ -209,3 +209,24 @@ def test_state_roundtrip_restart():
     want = oracle.Oracle(p).run("oci", steps=2, fixed_iters=5, psi_init=st)["phi"]
     assert rel(rest, want) <= 1e-12
     assert rel(full[:2], oracle.Oracle(p).run("oci", steps=2, fixed_iters=5)["phi"]) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", [{"OCI_MODE": "global"}, {"OCI_NO_RESIDENT": "1"},
+                                  {"OCI_BLOCK": "256"}, {"OCI_BAR_GROUP": "3"}])
+@pytest.mark.parametrize("name", ["regions512_n64", "multigroup128_n256", "odd_N6_n24"])
+def test_kernel_variants_lockstep(name, mode, monkeypatch):
+    """Every launch variant (global-memory kernel, streamed factors, block size,
+    barrier arrival groups) gives the oracle's lock-step answer."""
+    for k, v in mode.items():
+        monkeypatch.setenv(k, v)
+    p, steps = CASES[name]
+    K = 6
+    _announce(name, p, f"variant {mode} K={K}")
+    for prec, tol in ((B.OCI_FP64, 1e-12), (B.OCI_FP32_REFINED, None)):
+        s = B.Solver(p, precision=prec, fixed_iters=K)
+        got, infos = s.run(steps=steps)
+        s.close()
+        assert all(i["iterations"] == K and i["status"] == 0 for i in infos), infos
+        if tol is not None:
+            want = oracle.Oracle(p).run("oci", steps=steps, fixed_iters=K)["phi"]
+            assert rel(got, want) <= tol
