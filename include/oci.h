@@ -170,6 +170,56 @@ int oci_profile_read(oci_handle *h, double *ms, int32_t *steps);
 /* Release the host-side handle.  The workspace stays the caller's. */
 int oci_destroy(oci_handle *h);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent slab problems (uneven J, N, G; one precision) advanced
+ * together: every batched time step runs one persistent launch in which slab
+ * k is served by its own block of workgroups (sized in proportion to its
+ * factor bytes per iteration, J x (4NG)^2), with its own control block,
+ * barrier and stopping decision, so slabs converge independently.  The
+ * iteration of each slab is the same OCI iteration as oci_step (eq. oci,
+ * Algorithm 2), through the factors kept in global memory.  Steps can be
+ * captured once into a HIP graph and replayed. */
+typedef struct oci_batch oci_batch;
+
+/* Workspace bytes for nslab descriptions (all of one precision). */
+int oci_batch_workspace_bytes(int32_t nslab, const oci_desc *descs, size_t *bytes);
+
+/* Set up every slab (as oci_setup, each in its own part of the workspace)
+ * and lay out the batched launch.  Synchronises the stream.  Returns
+ * OCI_ERR_UNSUPPORTED when the slabs cannot all be given a co-resident
+ * workgroup. */
+int oci_batch_setup(int32_t nslab, const oci_desc *descs, void *workspace_dev,
+                    size_t workspace_bytes, void *stream, oci_batch **out);
+
+/* Bind the per-slab step arguments used by every later oci_batch_step and
+ * by a captured graph: host arrays of nslab device pointers (q, incident
+ * fluxes: entries or whole arrays may be NULL, as in oci_step; phi_out:
+ * required) and info_dev, nslab oci_step_info in device memory.  Uploads the
+ * launch table and synchronises the stream. */
+int oci_batch_bind(oci_batch *b, const double *const *q_dev, const double *const *inc_left_dev,
+                   const double *const *inc_right_dev, double *const *phi_out_dev,
+                   oci_step_info *info_dev);
+
+/* One time step of every slab (asynchronous; results in the bound outputs). */
+int oci_batch_step(oci_batch *b);
+
+/* Capture n_steps batched steps into a HIP graph held by the batch (needs a
+ * non-null stream), and launch it.  Replays continue from the current state;
+ * the bound outputs hold the last step's results. */
+int oci_batch_capture(oci_batch *b, int32_t n_steps);
+int oci_batch_replay(oci_batch *b);
+
+/* State of slab k, as oci_set_state / oci_get_state. */
+int oci_batch_set_state(oci_batch *b, int32_t k, const double *psi_prev_dev);
+int oci_batch_get_state(const oci_batch *b, int32_t k, double *psi_prev_dev);
+
+/* Launch geometry: total workgroups and, if nwg_per_slab is not NULL, the
+ * workgroups of each slab ([nslab]). */
+int oci_batch_info(const oci_batch *b, int32_t *nwg_total, int32_t *nwg_per_slab);
+
+/* Release the batch and its slab handles (the workspace stays the caller's). */
+int oci_batch_destroy(oci_batch *b);
+
 /* Static text for a status code. */
 const char *oci_status_string(int status);
 

@@ -26,7 +26,9 @@ OCI_NORM_SCALAR, OCI_NORM_ANGULAR = 0, 1
 # every symbol include/oci.h declares
 EXPORTS = ("oci_workspace_bytes", "oci_setup", "oci_set_state", "oci_get_state",
            "oci_step", "si_step", "oci_profile_enable", "oci_profile_read",
-           "oci_destroy", "oci_status_string")
+           "oci_destroy", "oci_batch_workspace_bytes", "oci_batch_setup", "oci_batch_bind",
+           "oci_batch_step", "oci_batch_capture", "oci_batch_replay", "oci_batch_set_state",
+           "oci_batch_get_state", "oci_batch_info", "oci_batch_destroy", "oci_status_string")
 
 
 class OciError(RuntimeError):
@@ -71,6 +73,16 @@ def lib():
         L.oci_profile_enable.argtypes = [vp, i32]
         L.oci_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.oci_destroy.argtypes = [vp]
+        L.oci_batch_workspace_bytes.argtypes = [i32, vp, C.POINTER(C.c_size_t)]
+        L.oci_batch_setup.argtypes = [i32, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.oci_batch_bind.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.oci_batch_step.argtypes = [vp]
+        L.oci_batch_capture.argtypes = [vp, i32]
+        L.oci_batch_replay.argtypes = [vp]
+        L.oci_batch_set_state.argtypes = [vp, i32, vp]
+        L.oci_batch_get_state.argtypes = [vp, i32, vp]
+        L.oci_batch_info.argtypes = [vp, vp, vp]
+        L.oci_batch_destroy.argtypes = [vp]
         L.oci_status_string.argtypes = [i32]
         L.oci_status_string.restype = C.c_char_p
         for name in EXPORTS:
@@ -162,6 +174,68 @@ def oci_destroy(h):
     _check("oci_destroy", lib().oci_destroy(h))
 
 
+def _desc_array(descs):
+    arr = (oci_desc * len(descs))(*descs)
+    return arr
+
+
+def oci_batch_workspace_bytes(descs):
+    n = C.c_size_t(0)
+    arr = _desc_array(descs)
+    _check("oci_batch_workspace_bytes", lib().oci_batch_workspace_bytes(len(descs), arr, C.byref(n)))
+    return n.value
+
+
+def oci_batch_setup(descs, workspace, nbytes, stream=None):
+    b = C.c_void_p()
+    arr = _desc_array(descs)
+    _check("oci_batch_setup", lib().oci_batch_setup(len(descs), arr, _ptr(workspace), int(nbytes),
+                                                    _ptr(stream), C.byref(b)))
+    return b
+
+
+def _ptr_array(xs):
+    if xs is None:
+        return None
+    return (C.c_void_p * len(xs))(*[_ptr(x) for x in xs])
+
+
+def oci_batch_bind(b, q, inc_left, inc_right, phi_out, info):
+    _check("oci_batch_bind", lib().oci_batch_bind(b, _ptr_array(q), _ptr_array(inc_left),
+                                                  _ptr_array(inc_right), _ptr_array(phi_out), _ptr(info)))
+
+
+def oci_batch_step(b):
+    _check("oci_batch_step", lib().oci_batch_step(b))
+
+
+def oci_batch_capture(b, n_steps):
+    _check("oci_batch_capture", lib().oci_batch_capture(b, int(n_steps)))
+
+
+def oci_batch_replay(b):
+    _check("oci_batch_replay", lib().oci_batch_replay(b))
+
+
+def oci_batch_set_state(b, k, psi_prev):
+    _check("oci_batch_set_state", lib().oci_batch_set_state(b, int(k), _ptr(psi_prev)))
+
+
+def oci_batch_get_state(b, k, psi_prev):
+    _check("oci_batch_get_state", lib().oci_batch_get_state(b, int(k), _ptr(psi_prev)))
+
+
+def oci_batch_info(b, nslab):
+    tot = C.c_int32(0)
+    per = (C.c_int32 * nslab)()
+    _check("oci_batch_info", lib().oci_batch_info(b, C.byref(tot), per))
+    return tot.value, list(per)
+
+
+def oci_batch_destroy(b):
+    _check("oci_batch_destroy", lib().oci_batch_destroy(b))
+
+
 def decode_info(raw):
     """oci_step_info from its 24 bytes (numpy uint8 array or bytes)."""
     b = bytes(np.asarray(raw, dtype=np.uint8).tobytes())
@@ -244,6 +318,89 @@ class Solver:
             self.stream.synchronize()
             oci_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchSolver:
+    """Device buffers and the liboci batch handle for a list of slab problems.
+
+    All slabs use one precision; steps run on a dedicated (default-priority)
+    stream so they can be captured into a graph.
+    """
+
+    def __init__(self, probs, precision=OCI_FP32_REFINED, tol=1e-10, max_iters=100000,
+                 fixed_iters=0, stream=None):
+        import torch
+        self.torch = torch
+        self.probs = probs
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.Stream() if stream is None else stream
+        made = [make_desc(p, tol=tol, max_iters=max_iters, fixed_iters=fixed_iters,
+                          precision=precision) for p in probs]
+        self.descs = [d for d, _ in made]
+        self._keep = [k for _, k in made]
+        self.ws_bytes = oci_batch_workspace_bytes(self.descs)
+        with torch.cuda.stream(self.stream):
+            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
+        off = (-self.ws.data_ptr()) % 256
+        self.b = oci_batch_setup(self.descs, self.ws.data_ptr() + off, self.ws_bytes,
+                                 self.stream.cuda_stream)
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        with torch.cuda.stream(self.stream):
+            self.q = [self._dev(p.get("q")) for p in probs]
+            self.inc_l = [self._dev(p.get("inc_left")) for p in probs]
+            self.inc_r = [self._dev(p.get("inc_right")) for p in probs]
+            self.phi = [torch.zeros((p["J"], p["G"], 4), **f64) for p in probs]
+            self.info = torch.zeros(24 * len(probs), dtype=torch.uint8, device=self.dev)
+        self.stream.synchronize()
+        oci_batch_bind(self.b, self.q, self.inc_l, self.inc_r, self.phi, self.info)
+
+    def _dev(self, a):
+        if a is None:
+            return None
+        return self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(self.dev)
+
+    def step(self):
+        oci_batch_step(self.b)
+
+    def capture(self, n_steps):
+        oci_batch_capture(self.b, n_steps)
+
+    def replay(self):
+        oci_batch_replay(self.b)
+
+    def results(self):
+        """(phi per slab as numpy, info per slab) after synchronising the stream."""
+        self.stream.synchronize()
+        raw = self.info.cpu().numpy()
+        return ([f.cpu().numpy() for f in self.phi],
+                [decode_info(raw[24 * k:24 * (k + 1)]) for k in range(len(self.probs))])
+
+    def get_state(self, k):
+        p = self.probs[k]
+        out = self.torch.empty((p["J"], p["G"], p["N"], 2), dtype=self.torch.float64, device=self.dev)
+        oci_batch_get_state(self.b, k, out)
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def set_state(self, k, psi_prev):
+        self._state = self._dev(psi_prev)
+        self.torch.cuda.synchronize()
+        oci_batch_set_state(self.b, k, self._state)
+
+    def geometry(self):
+        return oci_batch_info(self.b, len(self.probs))
+
+    def close(self):
+        if self.b is not None:
+            self.stream.synchronize()
+            oci_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

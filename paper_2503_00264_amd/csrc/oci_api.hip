@@ -28,6 +28,11 @@ bool resident_supported(bool fp32, int np);
 bool block_supported(int bs);
 hipError_t launch_si_iteration(const Slab &S, const StepIO &io, hipStream_t st);
 size_t si_flux_blocks(const Slab &S);
+hipError_t batch_occupancy(bool fp32, int *blocks);
+int batch_block();
+hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp32, bool broadcast, hipStream_t st,
+                             bool coop);
+hipError_t launch_flag_broadcast(const Slab &S, hipStream_t st);
 }  // namespace oci
 
 using namespace oci;
@@ -447,6 +452,199 @@ extern "C" int oci_destroy(oci_handle *h) {
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->h_flag) (void)hipHostFree(h->h_flag);
     delete h;
+    return OCI_OK;
+}
+
+// ================================================================ batches
+struct oci_batch {
+    int nslab;
+    bool fp32;
+    hipStream_t st;
+    std::vector<oci_handle *> slabs;
+    std::vector<BatchEntry> tab;   // host copy of the device table
+    BatchEntry *d_tab;             // in the workspace
+    int nwg;                       // workgroups of the batched launch
+    bool bound;
+    hipGraphExec_t graph;
+    int graph_steps;
+};
+
+static size_t batch_table_bytes(int nslab) { return align256((size_t)nslab * sizeof(BatchEntry)); }
+
+extern "C" int oci_batch_workspace_bytes(int32_t nslab, const oci_desc *descs, size_t *bytes) {
+    if (nslab < 1 || !descs || !bytes) return OCI_ERR_INVALID;
+    size_t tot = batch_table_bytes(nslab);
+    for (int k = 0; k < nslab; ++k) {
+        size_t b = 0;
+        const int rc = oci_workspace_bytes(&descs[k], &b);
+        if (rc) return rc;
+        if (descs[k].precision != descs[0].precision) return OCI_ERR_INVALID;
+        tot += align256(b);
+    }
+    *bytes = tot;
+    return OCI_OK;
+}
+
+extern "C" int oci_batch_destroy(oci_batch *b) {
+    if (!b) return OCI_ERR_INVALID;
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (oci_handle *h : b->slabs)
+        if (h) oci_destroy(h);
+    delete b;
+    return OCI_OK;
+}
+
+extern "C" int oci_batch_setup(int32_t nslab, const oci_desc *descs, void *workspace_dev, size_t workspace_bytes,
+                               void *stream, oci_batch **out) {
+    if (!out) return OCI_ERR_INVALID;
+    *out = nullptr;
+    size_t need = 0;
+    int rc = oci_batch_workspace_bytes(nslab, descs, &need);
+    if (rc) return rc;
+    if (!workspace_dev || ((uintptr_t)workspace_dev & 255) || workspace_bytes < need) return OCI_ERR_WORKSPACE;
+    oci_batch *b = new (std::nothrow) oci_batch();
+    if (!b) return OCI_ERR_HIP;
+    b->nslab = nslab;
+    b->fp32 = descs[0].precision == OCI_FP32_REFINED;
+    b->st = (hipStream_t)stream;
+    b->d_tab = (BatchEntry *)workspace_dev;
+    b->graph = nullptr;
+    unsigned char *ws = (unsigned char *)workspace_dev;
+    size_t off = batch_table_bytes(nslab);
+    for (int k = 0; k < nslab; ++k) {
+        size_t bk = 0;
+        oci_workspace_bytes(&descs[k], &bk);
+        oci_handle *h = nullptr;
+        rc = oci_setup(&descs[k], ws + off, align256(bk), stream, &h);
+        if (rc) { oci_batch_destroy(b); return rc; }
+        b->slabs.push_back(h);
+        off += align256(bk);
+    }
+    // workgroups: proportional to each slab's factor bytes per iteration
+    // (J np^2), at least one, at most its tile count, all co-resident
+    int occ = 0;
+    if (batch_occupancy(b->fp32, &occ) != hipSuccess || occ < 1) { oci_batch_destroy(b); return OCI_ERR_HIP; }
+    const int num_cu = b->slabs[0]->num_cu;
+    long cap = (long)occ * num_cu;
+    if (cap > (long)num_cu * 8) cap = (long)num_cu * 8;
+    if (nslab > cap) { oci_batch_destroy(b); return OCI_ERR_UNSUPPORTED; }
+    const int bs = batch_block();
+    std::vector<long> ntile(nslab), alloc(nslab);
+    double wsum = 0.0;
+    std::vector<double> wgt(nslab);
+    for (int k = 0; k < nslab; ++k) {
+        const oci_handle *h = b->slabs[k];
+        const int rpt = h->np > bs ? h->np / bs : 1;
+        const int cpt = bs / (h->np / rpt);
+        ntile[k] = (h->d.J + cpt - 1) / cpt;
+        wgt[k] = (double)h->d.J * h->np * h->np;
+        wsum += wgt[k];
+    }
+    long used = 0;
+    for (int k = 0; k < nslab; ++k) {
+        long a = (long)(wgt[k] / wsum * (double)cap);
+        if (a < 1) a = 1;
+        if (a > ntile[k]) a = ntile[k];
+        alloc[k] = a;
+        used += a;
+    }
+    while (used > cap) {   // trim the largest allocations
+        int kmax = 0;
+        for (int k = 1; k < nslab; ++k) if (alloc[k] > alloc[kmax]) kmax = k;
+        --alloc[kmax];
+        --used;
+    }
+    b->tab.resize(nslab);
+    int wg0 = 0;
+    for (int k = 0; k < nslab; ++k) {
+        BatchEntry &e = b->tab[k];
+        memset(&e, 0, sizeof(e));
+        e.S = b->slabs[k]->S;
+        e.S.bar_groups = (int)((alloc[k] + e.S.bar_gsz - 1) / e.S.bar_gsz);
+        e.ntiles = (int)ntile[k];
+        e.wg0 = wg0;
+        e.nwg = (int)alloc[k];
+        wg0 += e.nwg;
+    }
+    b->nwg = wg0;
+    b->bound = false;
+    *out = b;
+    return OCI_OK;
+}
+
+extern "C" int oci_batch_bind(oci_batch *b, const double *const *q_dev, const double *const *inc_left_dev,
+                              const double *const *inc_right_dev, double *const *phi_out_dev,
+                              oci_step_info *info_dev) {
+    if (!b || !phi_out_dev || !info_dev) return OCI_ERR_INVALID;
+    for (int k = 0; k < b->nslab; ++k) {
+        if (!phi_out_dev[k]) return OCI_ERR_INVALID;
+        StepIO &io = b->tab[k].io;
+        io.q = q_dev ? q_dev[k] : nullptr;
+        io.inc_l = inc_left_dev ? inc_left_dev[k] : nullptr;
+        io.inc_r = inc_right_dev ? inc_right_dev[k] : nullptr;
+        io.phi_out = phi_out_dev[k];
+        io.psi_out = nullptr;
+        io.info = info_dev + k;
+    }
+    if (hipMemcpyAsync(b->d_tab, b->tab.data(), sizeof(BatchEntry) * b->nslab, hipMemcpyHostToDevice, b->st) !=
+        hipSuccess)
+        return OCI_ERR_HIP;
+    if (hipStreamSynchronize(b->st) != hipSuccess) return OCI_ERR_HIP;
+    b->bound = true;
+    return OCI_OK;
+}
+
+extern "C" int oci_batch_step(oci_batch *b) {
+    if (!b || !b->bound) return OCI_ERR_INVALID;
+    HIPCHECK(launch_batch_step(b->d_tab, b->nslab, b->nwg, b->fp32, false, b->st, true));
+    return OCI_OK;
+}
+
+extern "C" int oci_batch_capture(oci_batch *b, int32_t n_steps) {
+    if (!b || !b->bound || n_steps < 1 || !b->st) return OCI_ERR_INVALID;
+    if (b->graph) { (void)hipGraphExecDestroy(b->graph); b->graph = nullptr; }
+    HIPCHECK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k)
+        e = launch_batch_step(b->d_tab, b->nslab, b->nwg, b->fp32, false, b->st, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->st, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return OCI_ERR_HIP;
+    }
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { b->graph = nullptr; return OCI_ERR_HIP; }
+    b->graph_steps = n_steps;
+    return OCI_OK;
+}
+
+extern "C" int oci_batch_replay(oci_batch *b) {
+    if (!b || !b->graph) return OCI_ERR_INVALID;
+    HIPCHECK(hipGraphLaunch(b->graph, b->st));
+    return OCI_OK;
+}
+
+extern "C" int oci_batch_set_state(oci_batch *b, int32_t k, const double *psi_prev_dev) {
+    if (!b || k < 0 || k >= b->nslab) return OCI_ERR_INVALID;
+    const int rc = oci_set_state(b->slabs[k], psi_prev_dev);
+    if (rc) return rc;
+    b->slabs[k]->need_broadcast = false;   // batched steps use the device flag
+    HIPCHECK(launch_flag_broadcast(b->slabs[k]->S, b->st));
+    return OCI_OK;
+}
+
+extern "C" int oci_batch_get_state(const oci_batch *b, int32_t k, double *psi_prev_dev) {
+    if (!b || k < 0 || k >= b->nslab) return OCI_ERR_INVALID;
+    return oci_get_state(b->slabs[k], psi_prev_dev);
+}
+
+extern "C" int oci_batch_info(const oci_batch *b, int32_t *nwg_total, int32_t *nwg_per_slab) {
+    if (!b || !nwg_total) return OCI_ERR_INVALID;
+    *nwg_total = b->nwg;
+    if (nwg_per_slab)
+        for (int k = 0; k < b->nslab; ++k) nwg_per_slab[k] = b->tab[k].nwg;
     return OCI_OK;
 }
 

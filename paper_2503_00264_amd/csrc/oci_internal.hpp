@@ -31,7 +31,9 @@ struct Ctl {
     double e_prev;         // e_{l-1}
     double e_last;         // e_l
     double rho;            // e_l / e_{l-1}
-    double pad[3];
+    int32_t bcast;         // batched steps: start the next step from psi_prev on both levels
+    int32_t pad0;
+    double pad[2];
 };
 static_assert(sizeof(Ctl) == 80, "Ctl layout");
 
@@ -73,6 +75,14 @@ struct StepIO {
     double *phi_out;             // [J][G][4]
     double *psi_out;             // [J][G][N][4] or null
     void *info;                  // oci_step_info*
+};
+
+// One slab of a batch: its view, its step inputs/outputs, and the block of
+// workgroups [wg0, wg0 + nwg) of the batched launch that serves it.
+struct BatchEntry {
+    Slab S;
+    StepIO io;
+    int32_t ntiles, wg0, nwg, pad;
 };
 
 // Element (r, c) of a cell's n x n factor block, stored as 16-byte vectors

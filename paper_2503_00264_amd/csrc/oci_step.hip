@@ -74,7 +74,7 @@ __device__ inline void decide(const Slab &S, double e) {
 
 // ------------------------------------------------------- step bookkeeping
 // Before a step: the first iterate is where the previous step ended.
-__global__ void k_begin_step(Slab S) {
+__device__ inline void begin_one(const Slab &S) {
     Ctl *c = S.ctl;
     c->base = (c->base + c->iter) & 1;
     c->iter = 0;
@@ -90,12 +90,10 @@ __global__ void k_begin_step(Slab S) {
     c->e_last = __builtin_nan("");
     c->rho = __builtin_nan("");
 }
+__global__ void k_begin_step(Slab S) { begin_one(S); }
 
 // phi of the first iterate: one thread per (j, g, u), m summed in order.
-__global__ __launch_bounds__(kBlock) void k_phi0(Slab S) {
-    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    const size_t total = (size_t)S.J * S.G * 4;
-    if (t >= total) return;
+__device__ inline void phi0_elem(const Slab &S, size_t t) {
     const int b = S.ctl->base;
     const int u = t & 3;
     const size_t jg = t >> 2;
@@ -104,21 +102,25 @@ __global__ __launch_bounds__(kBlock) void k_phi0(Slab S) {
     for (int m = 0; m < S.N; ++m) s += S.w[m] * p[m * 4];
     S.phi[b][t] = s;
 }
+__global__ __launch_bounds__(kBlock) void k_phi0(Slab S) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < (size_t)S.J * S.G * 4) phi0_elem(S, t);
+}
 
 // psi of the first iterate from the state (both time levels).
+__device__ inline void broadcast_elem(const Slab &S, size_t t) {
+    S.psi[S.ctl->base][t] = S.psi_prev[(t >> 2) * 2 + (t & 1)];
+}
 __global__ __launch_bounds__(kBlock) void k_broadcast_state(Slab S) {
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    const size_t total = (size_t)S.J * S.G * S.N * 4;
-    if (t >= total) return;
-    const int b = S.ctl->base;
-    S.psi[b][t] = S.psi_prev[(t >> 2) * 2 + (t & 1)];
+    if (t < (size_t)S.J * S.G * S.N * 4) broadcast_elem(S, t);
 }
 
 // After a step: time update psi_{k-1/2} <- psi_{k+1/2} and the outputs.
-__global__ __launch_bounds__(kBlock) void k_end_step(Slab S, StepIO io) {
+// Elements: one per (j, g, m) row quad and per phi entry.
+__device__ inline void end_elem(const Slab &S, const StepIO &io, size_t t) {
     const Ctl *c = S.ctl;
     const int fin = (c->base + c->iter) & 1;
-    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const size_t nrow = (size_t)S.J * S.G * S.N;
     if (t < nrow) {
         const double *p = S.psi[fin] + t * 4;
@@ -140,6 +142,14 @@ __global__ __launch_bounds__(kBlock) void k_end_step(Slab S, StepIO io) {
         dp[1] = c->e_last;
         dp[2] = c->rho;
     }
+}
+__device__ inline size_t end_elems(const Slab &S) {
+    const size_t a = (size_t)S.J * S.G * S.N, b = (size_t)S.J * S.G * 4;
+    return a > b ? a : b;
+}
+__global__ __launch_bounds__(kBlock) void k_end_step(Slab S, StepIO io) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < end_elems(S)) end_elem(S, io, t);
 }
 
 // -------------------------------------------------------------- OCI kernel
@@ -181,14 +191,14 @@ __device__ inline double block_sum_t(double v, double *s_tmp) {
 constexpr long kSpinLimit = 1L << 25;
 
 template <int BS>
-__device__ inline bool grid_sync_sum(const Slab &S, unsigned nwg, int l, double wg_sum, int *s_flag,
+__device__ inline bool grid_sync_sum(const Slab &S, unsigned wg, unsigned nwg, int l, double wg_sum, int *s_flag,
                                      double *s_tmp, double *total) {
     double *part = S.partials + (size_t)(l & 1) * nwg;
-    if (threadIdx.x == 0) part[blockIdx.x] = wg_sum;
+    if (threadIdx.x == 0) part[wg] = wg_sum;
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned gsz_all = (unsigned)S.bar_gsz;
-        const unsigned grp = blockIdx.x / gsz_all;
+        const unsigned grp = wg / gsz_all;
         const unsigned ngrp = (nwg + gsz_all - 1) / gsz_all;
         const unsigned gsz = (grp + 1 == ngrp) ? nwg - grp * gsz_all : gsz_all;
         const uint64_t round = (uint64_t)l + 1;
@@ -239,8 +249,7 @@ __device__ inline void lc_row(const Slab &S, int j, int g, double mu, int u, dou
 // step (one tile per workgroup); BS: threads per workgroup.  At most 128
 // VGPRs (4 waves per SIMD).
 template <typename T, int NP, bool RES, int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
-void k_oci_step(Slab S, StepIO io, int ntiles) {
+__device__ inline void oci_global_body(const Slab &S, const StepIO &io, int ntiles, int wg, unsigned nwg) {
     constexpr bool REF = sizeof(T) == 4;
     constexpr int RPT = NP > BS ? NP / BS : 1;   // rows per thread
     constexpr int TPC = NP / RPT;                 // threads per cell
@@ -266,8 +275,6 @@ void k_oci_step(Slab S, StepIO io, int ntiles) {
     const int cl = tid / TPC;
     const int t = tid % TPC;
     const int J = S.J, N = S.N, G = S.G, n = S.n;
-    const unsigned nwg = gridDim.x;
-    const int wg = blockIdx.x;
     const int tile0 = (int)(((long)ntiles * wg) / nwg);
     const int tile1 = (int)(((long)ntiles * (wg + 1)) / nwg);
 
@@ -449,7 +456,7 @@ void k_oci_step(Slab S, StepIO io, int ntiles) {
 
         // (5) grid barrier + reduction; every workgroup decides identically
         double tot = 0.0;
-        const bool ok = grid_sync_sum<BS>(S, nwg, l, wg_sum, s_flag, s_tmp, &tot);
+        const bool ok = grid_sync_sum<BS>(S, wg, nwg, l, wg_sum, s_flag, s_tmp, &tot);
         if (!ok) break;
         const int iters = l + 1;
         const double e = sqrt(tot);
@@ -473,6 +480,12 @@ void k_oci_step(Slab S, StepIO io, int ntiles) {
             break;
         }
     }
+}
+
+template <typename T, int NP, bool RES, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
+void k_oci_step(Slab S, StepIO io, int ntiles) {
+    oci_global_body<T, NP, RES, BS>(S, io, ntiles, blockIdx.x, gridDim.x);
 }
 
 // Relaxed agent-scope accesses: coherent across the XCDs without any L2
@@ -849,21 +862,20 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
 // Constant part of b for the current step (eq. rhs_sg without the incident
 // terms): dx/4 Q_u, plus dx/(2 v dt) psi_{k-1/2} in the level-k rows.  One
 // thread per row of every cell; used by every iteration of OCI and SI.
-__global__ __launch_bounds__(kBlock) void k_const_rhs(Slab S, StepIO io) {
-    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    const size_t total = (size_t)S.J * S.n;
-    if (t >= total) return;
+__device__ inline void const_rhs_elem(const Slab &S, const StepIO &io, size_t t) {
     const int u = t & 3;
     const size_t jgm = t >> 2;
-    const int m = jgm % S.N;
     const size_t jg = jgm / S.N;
     const int g = jg % S.G;
     const int j = jg / S.G;
     const double dx = S.dx[j];
     double c = io.q ? 0.25 * dx * io.q[jg * 4 + u] : 0.0;
     if (u < 2) c += dx / (2.0 * S.speed[g] * S.dt) * S.psi_prev[jgm * 2 + u];
-    (void)m;
     S.crhs[t] = c;
+}
+__global__ __launch_bounds__(kBlock) void k_const_rhs(Slab S, StepIO io) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < (size_t)S.J * S.n) const_rhs_elem(S, io, t);
 }
 
 // --------------------------------------------------------------- SI kernels
@@ -947,6 +959,107 @@ __global__ __launch_bounds__(kBlock) void k_si_flux(Slab S) {
         c->bar_count = 0;
         decide(S, sqrt(tot));
     }
+}
+
+// ------------------------------------------------------------ batched slabs
+// Many independent slab problems (uneven J, N, G) in one persistent launch.
+// Slab k owns the workgroups [wg0, wg0 + nwg) of the grid; each runs the
+// global-memory iteration body of its own cell size on its own control block,
+// partial sums and barrier counters, so slabs converge independently and the
+// launch ends when the last one has.
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
+void k_oci_batch(const BatchEntry *tab, int nslab) {
+    __shared__ int s_k;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = nslab - 1;     // last entry with wg0 <= blockIdx.x
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[mid].wg0 <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+        }
+        s_k = lo;
+    }
+    __syncthreads();
+    const BatchEntry &e = tab[s_k];
+    const int lw = (int)blockIdx.x - e.wg0;
+    if (lw < 0 || lw >= e.nwg) return;
+    const Slab S = e.S;
+    const StepIO io = e.io;
+    switch (S.np) {
+    case 8: oci_global_body<T, 8, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
+    case 16: oci_global_body<T, 16, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
+    case 32: oci_global_body<T, 32, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
+    case 64: oci_global_body<T, 64, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
+    case 128: oci_global_body<T, 128, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
+    case 256: oci_global_body<T, 256, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
+    case 512: oci_global_body<T, 512, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
+    default: break;
+    }
+}
+
+// Bookkeeping over every slab of the table: blockIdx.y = slab, grid-stride x.
+__global__ void k_batch_begin(const BatchEntry *tab) { begin_one(tab[blockIdx.x].S); }
+
+__global__ __launch_bounds__(kBlock) void k_batch_elems(const BatchEntry *tab, int what, int broadcast) {
+    const BatchEntry &e = tab[blockIdx.y];
+    const Slab &S = e.S;
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    const size_t t0 = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (what == 0) {           // first iterate (when the state was replaced) and the constant RHS
+        if (broadcast || S.ctl->bcast)
+            for (size_t t = t0; t < (size_t)S.J * S.n; t += stride) broadcast_elem(S, t);
+        for (size_t t = t0; t < (size_t)S.J * S.n; t += stride) const_rhs_elem(S, e.io, t);
+    } else if (what == 1) {    // phi of the first iterate
+        for (size_t t = t0; t < (size_t)S.J * S.G * 4; t += stride) phi0_elem(S, t);
+        if (t0 == 0) S.ctl->bcast = 0;
+    } else {                   // end of step
+        const size_t ne = end_elems(S);
+        for (size_t t = t0; t < ne; t += stride) end_elem(S, e.io, t);
+    }
+}
+
+template <typename T, int BS>
+static hipError_t batch_launch_t(const BatchEntry *tab, int nslab, int nwg, hipStream_t st, bool coop) {
+    if (coop) {
+        void *args[] = {(void *)&tab, (void *)&nslab};
+        return hipLaunchCooperativeKernel((const void *)&k_oci_batch<T, BS>, dim3(nwg), dim3(BS), args, 0, st);
+    }
+    hipLaunchKernelGGL((k_oci_batch<T, BS>), dim3(nwg), dim3(BS), 0, st, tab, nslab);
+    return hipGetLastError();
+}
+
+constexpr int kBatchBlock = 256;
+
+hipError_t batch_occupancy(bool fp32, int *blocks) {
+    return fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)&k_oci_batch<float, kBatchBlock>,
+                                                              kBatchBlock, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)&k_oci_batch<double, kBatchBlock>,
+                                                              kBatchBlock, 0);
+}
+
+int batch_block() { return kBatchBlock; }
+
+__global__ void k_flag_broadcast(Slab S) { S.ctl->bcast = 1; }
+hipError_t launch_flag_broadcast(const Slab &S, hipStream_t st) {
+    hipLaunchKernelGGL(k_flag_broadcast, dim3(1), dim3(1), 0, st, S);
+    return hipGetLastError();
+}
+
+// One batched time step: bookkeeping for all slabs, the persistent launch,
+// the end-of-step kernel.  No memset and no host synchronisation, so the
+// sequence can be captured into a graph (then with a normal launch).
+hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp32, bool broadcast, hipStream_t st,
+                             bool coop) {
+    hipLaunchKernelGGL(k_batch_begin, dim3(nslab), dim3(1), 0, st, tab);
+    hipLaunchKernelGGL(k_batch_elems, dim3(256, nslab), dim3(kBlock), 0, st, tab, 0, broadcast ? 1 : 0);
+    hipLaunchKernelGGL(k_batch_elems, dim3(64, nslab), dim3(kBlock), 0, st, tab, 1, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = fp32 ? batch_launch_t<float, kBatchBlock>(tab, nslab, nwg, st, coop)
+             : batch_launch_t<double, kBatchBlock>(tab, nslab, nwg, st, coop);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_elems, dim3(256, nslab), dim3(kBlock), 0, st, tab, 2, 0);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- launchers
