@@ -167,6 +167,21 @@ int oci_profile_enable(oci_handle *h, int on);
  * the number of steps recorded in *steps; then forget them. */
 int oci_profile_read(oci_handle *h, double *ms, int32_t *steps);
 
+/* Autotuner: time the candidate launch shapes of the persistent OCI kernel
+ * on this handle's own problem and keep the fastest.  Candidates: 256 or
+ * 1024 threads per workgroup (4 or 16 cells per tile at n <= 64), the
+ * workgroup-local kernel with register-resident or streamed inverse rows or
+ * the global-memory kernel, and barrier arrival groups of 16 or 64
+ * workgroups.  Each runs `iters` iterations of one step from the zero state
+ * (no stopping test), timed with HIP events.  Synchronises the stream; the
+ * state is zero afterwards (call it right after oci_setup).  config, if not
+ * NULL, receives the chosen shape as oci_get_config reports it. */
+int oci_autotune(oci_handle *h, int32_t iters, int32_t *config);
+
+/* Current launch shape: config[6] = {threads per workgroup, local kernel (0/1),
+ * register-resident rows (0/1), barrier group size, workgroups, tiles}. */
+int oci_get_config(const oci_handle *h, int32_t *config);
+
 /* Release the host-side handle.  The workspace stays the caller's. */
 int oci_destroy(oci_handle *h);
 

@@ -26,7 +26,7 @@ OCI_NORM_SCALAR, OCI_NORM_ANGULAR = 0, 1
 # every symbol include/oci.h declares
 EXPORTS = ("oci_workspace_bytes", "oci_setup", "oci_set_state", "oci_get_state",
            "oci_step", "si_step", "oci_profile_enable", "oci_profile_read",
-           "oci_destroy", "oci_batch_workspace_bytes", "oci_batch_setup", "oci_batch_bind",
+           "oci_autotune", "oci_get_config", "oci_destroy", "oci_batch_workspace_bytes", "oci_batch_setup", "oci_batch_bind",
            "oci_batch_step", "oci_batch_capture", "oci_batch_replay", "oci_batch_set_state",
            "oci_batch_get_state", "oci_batch_info", "oci_batch_destroy", "oci_status_string")
 
@@ -73,6 +73,8 @@ def lib():
         L.oci_profile_enable.argtypes = [vp, i32]
         L.oci_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.oci_destroy.argtypes = [vp]
+        L.oci_autotune.argtypes = [vp, i32, vp]
+        L.oci_get_config.argtypes = [vp, vp]
         L.oci_batch_workspace_bytes.argtypes = [i32, vp, C.POINTER(C.c_size_t)]
         L.oci_batch_setup.argtypes = [i32, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.oci_batch_bind.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -168,6 +170,21 @@ def oci_profile_read(h):
     ms, n = C.c_double(0.0), C.c_int32(0)
     _check("oci_profile_read", lib().oci_profile_read(h, C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+CONFIG_FIELDS = ("block", "local", "resident", "bar_group", "workgroups", "tiles")
+
+
+def oci_autotune(h, iters=8):
+    cfg = (C.c_int32 * 6)()
+    _check("oci_autotune", lib().oci_autotune(h, int(iters), cfg))
+    return dict(zip(CONFIG_FIELDS, list(cfg)))
+
+
+def oci_get_config(h):
+    cfg = (C.c_int32 * 6)()
+    _check("oci_get_config", lib().oci_get_config(h, cfg))
+    return dict(zip(CONFIG_FIELDS, list(cfg)))
 
 
 def oci_destroy(h):
@@ -312,6 +329,13 @@ class Solver:
         self.stream.synchronize()
         return (self.torch.stack(phis).cpu().numpy(),
                 [decode_info(i.cpu().numpy()) for i in infos])
+
+    def autotune(self, iters=8):
+        """Pick the fastest launch shape (state is zero afterwards)."""
+        return oci_autotune(self.h, iters)
+
+    def config(self):
+        return oci_get_config(self.h)
 
     def close(self):
         if self.h is not None:

@@ -141,7 +141,8 @@ static void gauss_legendre(int N, double *mu, double *w) {
 
 // --------------------------------------------------------------- workspace
 struct Layout {
-    size_t ctl, bar, mu, w, dx, st, ss, sp, X, psi0, psi1, phi0, phi1, prev, crhs, exch, linv, part, total;
+    size_t ctl, bar, mu, w, dx, st, ss, sp, X, psi0, psi1, phi0, phi1, prev, crhs, exch, linv, resp, msw, alpha, ein,
+        part, total;
     int bar_groups;
 };
 
@@ -177,6 +178,10 @@ static Layout layout(const oci_desc *d, int num_cu) {
     L.crhs = take(J * n * 8);
     L.exch = take((size_t)2 * num_cu * 8 * 2 * N * G * 8);
     L.linv = take(J * G * N * 16 * 8);
+    L.resp = take(J * G * N * 8 * 8);
+    L.msw = take(J * G * N * 4 * 8);
+    L.alpha = take(J * G * N * 2 * 8);
+    L.ein = take(J * G * N * 2 * 8);
     const size_t si_blocks = (J * G * 4 + kBlock - 1) / kBlock;
     size_t parts = (size_t)num_cu * 8 * 2;
     if (si_blocks > parts) parts = si_blocks;
@@ -197,6 +202,75 @@ extern "C" int oci_workspace_bytes(const oci_desc *desc, size_t *bytes) {
     do {                                             \
         if ((x) != hipSuccess) return OCI_ERR_HIP;   \
     } while (0)
+
+// Launch geometry of the persistent OCI kernel for one block size: prefer
+// the workgroup-local kernel (iterate in LDS) with register-resident
+// inverse rows, then local with streamed rows, then the global-memory kernel
+// (resident, then streamed).  One tile = block / (threads per cell) cells.
+static int configure(oci_handle *h, int block, bool allow_local, bool allow_res, int gsz) {
+    const int num_cu = h->num_cu;
+    const int N = h->d.N, G = h->d.G;
+    const int rpt = h->np > block ? h->np / block : 1;
+    const int tpc = h->np / rpt;
+    const int cpt = block / tpc;
+    const long ntiles = (h->d.J + cpt - 1) / cpt;
+    const long wg_cap = (long)num_cu * 8;  // partial-sum and exchange slots in the workspace
+    int occ_res = 0, occ = 0;
+    if (oci_occupancy(h->fp32, h->np, false, block, &occ) != hipSuccess || occ < 1) return OCI_ERR_HIP;
+    bool local = false, res = false;
+    long nwg = 0;
+    size_t dyn_lds = 0;
+    // dynamic LDS of the local kernel: cells x (n + 4G) + tiles x 2NG doubles
+    auto try_local = [&](bool r) -> bool {
+        size_t stat = 0;
+        if (local_static_lds(h->fp32, h->np, r, block, &stat) != hipSuccess) return false;
+        const size_t lds_max = 160 * 1024;
+        int occ0 = 0;
+        if (local_occupancy(h->fp32, h->np, r, block, 0, &occ0) != hipSuccess || occ0 < 1) return false;
+        long w = ntiles < (long)occ0 * num_cu ? ntiles : (long)occ0 * num_cu;
+        if (w > wg_cap) w = wg_cap;
+        for (int it = 0; it < 8 && w >= 1; ++it) {
+            const long tpw = (ntiles + w - 1) / w;
+            const size_t dyn = ((size_t)tpw * cpt * (h->n + 4 * G) + (size_t)tpw * 2 * N * G) * 8;
+            if (stat + dyn > lds_max) return false;
+            int o = 0;
+            if (local_occupancy(h->fp32, h->np, r, block, dyn, &o) != hipSuccess || o < 1) return false;
+            if ((long)o * num_cu >= w) {
+                if (r && w != ntiles) return false;
+                nwg = w;
+                dyn_lds = dyn;
+                return true;
+            }
+            if (r) return false;
+            w = (long)o * num_cu;
+        }
+        return false;
+    };
+    if (allow_local && allow_res && resident_supported(h->fp32, h->np) && try_local(true)) {
+        local = res = true;
+    } else if (allow_local && try_local(false)) {
+        local = true;
+    } else if (allow_res && resident_supported(h->fp32, h->np) &&
+               oci_occupancy(h->fp32, h->np, true, block, &occ_res) == hipSuccess &&
+               (long)occ_res * num_cu >= ntiles && ntiles <= wg_cap) {
+        res = true;
+        nwg = ntiles;
+    } else {
+        const long cap = (long)occ * num_cu;
+        nwg = ntiles < cap ? ntiles : cap;
+    }
+    if (nwg > wg_cap) nwg = wg_cap;
+    if (nwg < 1) return OCI_ERR_UNSUPPORTED;
+    h->block = block;
+    h->ntiles = (int)ntiles;
+    h->nwg = (int)nwg;
+    h->local = local;
+    h->resident = res;
+    h->dyn_lds = dyn_lds;
+    h->S.bar_gsz = gsz;
+    h->S.bar_groups = (h->nwg + gsz - 1) / gsz;  // counters the barrier uses
+    return OCI_OK;
+}
 
 extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t workspace_bytes, void *stream,
                          oci_handle **out) {
@@ -244,6 +318,10 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
     S.crhs = (double *)(ws + L.crhs);
     S.exch = (double *)(ws + L.exch);
     S.si_linv = (double *)(ws + L.linv);
+    S.si_resp = (double *)(ws + L.resp);
+    S.si_msw = (double *)(ws + L.msw);
+    S.si_alpha = (double *)(ws + L.alpha);
+    S.si_ein = (double *)(ws + L.ein);
     S.partials = (double *)(ws + L.part);
     S.ctl = (Ctl *)(ws + L.ctl);
     S.bar = (uint64_t *)(ws + L.bar);
@@ -284,73 +362,17 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
     if (hipMemcpy(&c, S.ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) { oci_destroy(h); return OCI_ERR_HIP; }
     if (c.singular) { oci_destroy(h); return OCI_ERR_SINGULAR; }
 
-    // persistent launch geometry: one tile = block / (threads per cell) cells;
-    // OCI_BLOCK (256 or 1024) overrides the block size
-    h->block = 1024;
+    // persistent launch geometry; environment overrides: OCI_BLOCK (256 or
+    // 1024), OCI_MODE=global, OCI_NO_RESIDENT=1 (OCI_BAR_GROUP read above)
+    int block = 1024;
     if (const char *env = getenv("OCI_BLOCK")) {
         const int b = atoi(env);
-        if (block_supported(b)) h->block = b;
+        if (block_supported(b)) block = b;
     }
-    const int rpt = h->np > h->block ? h->np / h->block : 1;
-    const int tpc = h->np / rpt;
-    const int cpt = h->block / tpc;
-    h->ntiles = (desc->J + cpt - 1) / cpt;
-    int occ_res = 0, occ = 0;
-    if (oci_occupancy(h->fp32, h->np, false, h->block, &occ) != hipSuccess || occ < 1) {
-        oci_destroy(h);
-        return OCI_ERR_HIP;
-    }
-    const long wg_cap = (long)num_cu * 8;  // partial-sum and exchange slots in the workspace
     const char *nores = getenv("OCI_NO_RESIDENT");
     const char *mode = getenv("OCI_MODE");
-    const bool allow_res = !(nores && atoi(nores));
-    const bool allow_local = !(mode && strcmp(mode, "global") == 0);
-    h->resident = false;
-    h->local = false;
-    h->dyn_lds = 0;
-    // workgroup-local kernel: the iterate of every owned cell lives in LDS
-    // (dynamic part: cells x (n + 4G) + tiles x 2NG doubles)
-    auto try_local = [&](bool res) -> bool {
-        size_t stat = 0;
-        if (local_static_lds(h->fp32, h->np, res, h->block, &stat) != hipSuccess) return false;
-        const size_t lds_max = 160 * 1024;
-        int occ0 = 0;
-        if (local_occupancy(h->fp32, h->np, res, h->block, 0, &occ0) != hipSuccess || occ0 < 1) return false;
-        long nwg = h->ntiles < (long)occ0 * num_cu ? h->ntiles : (long)occ0 * num_cu;
-        if (nwg > wg_cap) nwg = wg_cap;
-        for (int it = 0; it < 8 && nwg >= 1; ++it) {
-            const long tpw = (h->ntiles + nwg - 1) / nwg;
-            const size_t dyn = ((size_t)tpw * cpt * (h->n + 4 * desc->G) + (size_t)tpw * 2 * desc->N * desc->G) * 8;
-            if (stat + dyn > lds_max) return false;
-            int occ = 0;
-            if (local_occupancy(h->fp32, h->np, res, h->block, dyn, &occ) != hipSuccess || occ < 1) return false;
-            if ((long)occ * num_cu >= nwg) {
-                if (res && nwg != h->ntiles) return false;
-                h->nwg = (int)nwg;
-                h->dyn_lds = dyn;
-                return true;
-            }
-            if (res) return false;
-            nwg = (long)occ * num_cu;
-        }
-        return false;
-    };
-    if (allow_local && allow_res && resident_supported(h->fp32, h->np) && try_local(true)) {
-        h->local = true;
-        h->resident = true;
-    } else if (allow_local && try_local(false)) {
-        h->local = true;
-    } else if (allow_res && resident_supported(h->fp32, h->np) &&
-               oci_occupancy(h->fp32, h->np, true, h->block, &occ_res) == hipSuccess &&
-               (long)occ_res * num_cu >= h->ntiles && h->ntiles <= wg_cap) {
-        h->resident = true;
-        h->nwg = h->ntiles;
-    } else {
-        const long cap = (long)occ * num_cu;
-        h->nwg = (int)(h->ntiles < cap ? h->ntiles : cap);
-    }
-    if (h->nwg > wg_cap) h->nwg = (int)wg_cap;
-    S.bar_groups = (h->nwg + S.bar_gsz - 1) / S.bar_gsz;  // counters the barrier uses
+    rc = configure(h, block, !(mode && strcmp(mode, "global") == 0), !(nores && atoi(nores)), S.bar_gsz);
+    if (rc) { oci_destroy(h); return rc; }
     h->need_broadcast = true;
     *out = h;
     return OCI_OK;
@@ -444,6 +466,73 @@ extern "C" int oci_profile_read(oci_handle *h, double *ms, int32_t *steps) {
     *ms = tot;
     *steps = (int32_t)(h->ev_used / 2);
     h->ev_used = 0;
+    return OCI_OK;
+}
+
+// Candidate launch shapes are timed on the handle's own problem: each runs
+// `iters` iterations of one step (no stopping test) from the zero state,
+// bracketed by HIP events; the fastest is kept.  The state is zero again
+// afterwards.
+extern "C" int oci_autotune(oci_handle *h, int32_t iters, int32_t *config) {
+    if (!h || iters < 1) return OCI_ERR_INVALID;
+    struct Cand { int block; bool local, res; int gsz; };
+    std::vector<Cand> cands;
+    for (int block : {1024, 256})
+        for (int gsz : {16, 64})
+            for (int lr = 0; lr < 3; ++lr)
+                cands.push_back(Cand{block, lr < 2, lr == 0, gsz});
+    const int32_t saved_fixed = h->S.fixed_iters;
+    const bool saved_prof = h->profiling;
+    h->profiling = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return OCI_ERR_HIP;
+    float best = 1e30f;
+    int best_k = -1;
+    StepIO io{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int rc = OCI_OK;
+    for (size_t k = 0; k < cands.size() && rc == OCI_OK; ++k) {
+        const Cand &c = cands[k];
+        if (configure(h, c.block, c.local, c.res, c.gsz) != OCI_OK) continue;
+        if (c.local != h->local || c.res != h->resident) continue;   // shape not available: skip duplicate
+        h->S.fixed_iters = iters;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && rc == OCI_OK; ++rep) {   // first run warms up
+            if (oci_set_state(h, nullptr) != OCI_OK) { rc = OCI_ERR_HIP; break; }
+            if (launch_begin(h->S, io, true, h->st) != hipSuccess) { rc = OCI_ERR_HIP; break; }
+            h->need_broadcast = false;
+            if (hipEventRecord(e0, h->st) != hipSuccess) { rc = OCI_ERR_HIP; break; }
+            hipError_t e = h->local ? launch_oci_local(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg,
+                                                       h->ntiles, h->dyn_lds, h->st)
+                                    : launch_oci_step(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg,
+                                                      h->ntiles, h->st, true);
+            if (e != hipSuccess || hipEventRecord(e1, h->st) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                rc = OCI_ERR_HIP;
+        }
+        if (rc == OCI_OK && ms < best) { best = ms; best_k = (int)k; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->S.fixed_iters = saved_fixed;
+    h->profiling = saved_prof;
+    if (rc != OCI_OK) return rc;
+    if (best_k < 0) return OCI_ERR_UNSUPPORTED;
+    const Cand &c = cands[best_k];
+    rc = configure(h, c.block, c.local, c.res, c.gsz);
+    if (rc) return rc;
+    if (oci_set_state(h, nullptr) != OCI_OK) return OCI_ERR_HIP;
+    if (config) oci_get_config(h, config);
+    return OCI_OK;
+}
+
+extern "C" int oci_get_config(const oci_handle *h, int32_t *config) {
+    if (!h || !config) return OCI_ERR_INVALID;
+    config[0] = h->block;
+    config[1] = h->local ? 1 : 0;
+    config[2] = h->resident ? 1 : 0;
+    config[3] = h->S.bar_gsz;
+    config[4] = h->nwg;
+    config[5] = h->ntiles;
     return OCI_OK;
 }
 

@@ -55,6 +55,10 @@ struct Slab {
     double *crhs;                // [J][G][N][4] constant part of b for the current step
     double *exch;                // [2][max workgroups][2][2][G][N/2] boundary edges between workgroups
     double *si_linv;             // [J][G][N][16] inverse of the 4x4 SI cell matrix
+    double *si_resp;             // [J][G][N][8] response of the cell to its two incident edges
+    double *si_msw;              // [J][NG][4] 2x2 edge-to-edge map, in sweep order
+    double *si_alpha;            // [J][NG][2] outgoing edges of the uncoupled solution, sweep order
+    double *si_ein;              // [J][NG][2] incident edges met by the sweep, sweep order
     double *partials;            // [2][max workgroups] per-workgroup sums (iteration parity)
     Ctl *ctl;
     // grid barrier words, 256 bytes apart: [0] arrivals of group leaders,

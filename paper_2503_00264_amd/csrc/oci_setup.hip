@@ -249,6 +249,25 @@ __global__ __launch_bounds__(kBlock) void k_si_invert(Slab S) {
     double *out = S.si_linv + t * 16;
     for (int r = 0; r < 4; ++r)
         for (int c = 0; c < 4; ++c) out[r * 4 + c] = M[r][4 + c];
+    // response to the incident edges (levels k, k+1/2): mu > 0 enters rows 0
+    // and 2 with +mu, mu < 0 enters rows 1 and 3 with -mu (eq. si_rhs)
+    const bool pos = mu > 0.0;
+    const int ca = pos ? 0 : 1, cb = pos ? 2 : 3;
+    const double f = pos ? mu : -mu;
+    double *rs = S.si_resp + t * 8;
+    for (int r = 0; r < 4; ++r) {
+        rs[r] = M[r][4 + ca] * f;
+        rs[4 + r] = M[r][4 + cb] * f;
+    }
+    // the 2x2 map from incident to outgoing edges, stored in sweep order
+    const int o0 = pos ? 1 : 0, o1 = pos ? 3 : 2;
+    const int NG = S.N * S.G;
+    const int step = pos ? j : S.J - 1 - j;
+    double *mw = S.si_msw + ((size_t)step * NG + g * S.N + m) * 4;
+    mw[0] = rs[o0];
+    mw[1] = rs[4 + o0];
+    mw[2] = rs[o1];
+    mw[3] = rs[4 + o1];
 }
 
 // ---------------------------------------------------------------- launchers

@@ -879,47 +879,106 @@ __global__ __launch_bounds__(kBlock) void k_const_rhs(Slab S, StepIO io) {
 }
 
 // --------------------------------------------------------------- SI kernels
-// One thread per (g, m) chain sweeping all cells in its direction.
-__global__ __launch_bounds__(64) void k_si_sweep(Slab S, StepIO io) {
+// Source iteration (Appendix A, Algorithm 1) with the scattering source of
+// the previous iterate.  Each (group, angle) chain is swept cell by cell, as
+// in the paper, but the work that does not depend on the incoming edge runs
+// in parallel around the serial part:
+//   k_si_pre    every cell: d = constant RHS + dx/4 sum_g' Ss phi^(l), the
+//               uncoupled solution base = L_c^-1 d and its outgoing edges
+//   k_si_sweep  one workgroup: the chains run e_out = alpha + M e_in cell by
+//               cell (M: the 2x2 edge-to-edge map of the cell), reading
+//               alpha and M from an LDS ring that the other waves fill ahead
+//               of them; the incident edge met at every cell is recorded
+//   k_si_flux   every (cell, group, corner/level): psi = base + response x
+//               incident edge, phi = sum_m w_m psi, its change, the decision
+__global__ __launch_bounds__(kBlock) void k_si_pre(Slab S) {
     const Ctl *c = S.ctl;
     if (c->done) return;
     const int cur = (c->base + c->iter) & 1;
-    const int k = blockIdx.x * 64 + threadIdx.x;
-    const int N = S.N, G = S.G, J = S.J;
-    if (k >= N * G) return;
-    const int g = k / N, m = k % N;
-    const double mu = S.mu[m];
-    const bool pos = mu > 0.0;
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int N = S.N, G = S.G;
+    if (t >= (size_t)S.J * G * N) return;
+    const int m = t % N, g = (t / N) % G, j = t / ((size_t)N * G);
+    const size_t jg = (size_t)j * G + g;
     const double *phi_in = S.phi[cur];
-    double *psi_out = S.psi[cur ^ 1];
-    double e0, e1;
-    if (pos) {
-        e0 = io.inc_l ? io.inc_l[(size_t)g * (N / 2) + (m - N / 2)] : 0.0;
-        e1 = io.inc_l ? io.inc_l[((size_t)G + g) * (N / 2) + (m - N / 2)] : 0.0;
-    } else {
-        e0 = io.inc_r ? io.inc_r[(size_t)g * (N / 2) + m] : 0.0;
-        e1 = io.inc_r ? io.inc_r[((size_t)G + g) * (N / 2) + m] : 0.0;
+    const double *cr = S.crhs + t * 4;
+    const double dx4 = 0.25 * S.dx[j];
+    double d[4];
+    for (int u = 0; u < 4; ++u) {
+        double sc = 0.0;
+        for (int gp = 0; gp < G; ++gp) sc += S.sigma_s[jg * G + gp] * phi_in[((size_t)j * G + gp) * 4 + u];
+        d[u] = cr[u] + dx4 * sc;
     }
-    for (int s = 0; s < J; ++s) {
-        const int j = pos ? s : J - 1 - s;
-        const size_t jg = (size_t)j * G + g;
-        const double dx = S.dx[j];
-        const double *cr = S.crhs + (jg * N + m) * 4;
-        double d[4];
-        for (int u = 0; u < 4; ++u) {
-            double sc = 0.0;
-            for (int gp = 0; gp < G; ++gp) sc += S.sigma_s[jg * G + gp] * phi_in[((size_t)j * G + gp) * 4 + u];
-            d[u] = cr[u] + 0.25 * dx * sc;
+    const double *Li = S.si_linv + t * 16;
+    double x[4];
+    for (int r = 0; r < 4; ++r) x[r] = Li[r * 4 + 0] * d[0] + Li[r * 4 + 1] * d[1] + Li[r * 4 + 2] * d[2] + Li[r * 4 + 3] * d[3];
+    double *o = S.psi[cur ^ 1] + t * 4;
+    o[0] = x[0]; o[1] = x[1]; o[2] = x[2]; o[3] = x[3];
+    const bool pos = S.mu[m] > 0.0;
+    const int step = pos ? j : S.J - 1 - j;
+    double *al = S.si_alpha + ((size_t)step * N * G + g * N + m) * 2;
+    al[0] = pos ? x[1] : x[0];
+    al[1] = pos ? x[3] : x[2];
+}
+
+constexpr int kSweepBlock = 1024;
+
+// One workgroup.  LDS ring: [2][C][NG][6] doubles (alpha0, alpha1, M00, M01,
+// M10, M11 per chain and sweep step).  Waves at or after the first wave
+// without chains fill buffer (c+1) & 1 while the chain lanes consume c & 1.
+__global__ __launch_bounds__(kSweepBlock) void k_si_sweep(Slab S, StepIO io, int C) {
+    extern __shared__ __align__(16) double s_ring[];
+    const Ctl *ctl = S.ctl;
+    if (ctl->done) return;
+    const int N = S.N, G = S.G, J = S.J, NG = N * G, nh = N / 2;
+    const int tid = threadIdx.x;
+    const int chain_waves = (NG + 63) / 64;
+    const int prod0 = chain_waves * 64;                  // first producer thread
+    const int nprod = kSweepBlock - prod0;
+    const size_t per_step = (size_t)NG * 6;
+    const int nchunks = (J + C - 1) / C;
+    auto fill = [&](int chunk, int buf, int first, int stride) {
+        double *dst = s_ring + (size_t)buf * C * per_step;
+        const int s0 = chunk * C;
+        const int ns = min(C, J - s0);
+        const size_t tot = (size_t)ns * per_step;
+        for (size_t idx = first; idx < tot; idx += stride) {
+            const int sl = idx / per_step;
+            const int r = idx % per_step;
+            const int k = r / 6, q = r % 6;
+            const size_t st = (size_t)(s0 + sl) * NG + k;
+            dst[idx] = q < 2 ? S.si_alpha[st * 2 + q] : S.si_msw[st * 4 + (q - 2)];
         }
-        if (pos) { d[0] += mu * e0; d[2] += mu * e1; }
-        else { d[1] -= mu * e0; d[3] -= mu * e1; }
-        const double *Li = S.si_linv + (jg * N + m) * 16;
-        double x[4];
-        for (int r = 0; r < 4; ++r) x[r] = Li[r * 4 + 0] * d[0] + Li[r * 4 + 1] * d[1] + Li[r * 4 + 2] * d[2] + Li[r * 4 + 3] * d[3];
-        double *o = psi_out + (jg * N + m) * 4;
-        o[0] = x[0]; o[1] = x[1]; o[2] = x[2]; o[3] = x[3];
-        e0 = pos ? x[1] : x[0];
-        e1 = pos ? x[3] : x[2];
+    };
+    double e0 = 0.0, e1 = 0.0;
+    if (tid < NG) {
+        const int g = tid / N, m = tid % N;
+        if (S.mu[m] > 0.0) {
+            if (io.inc_l) { e0 = io.inc_l[(size_t)g * nh + (m - nh)]; e1 = io.inc_l[((size_t)G + g) * nh + (m - nh)]; }
+        } else {
+            if (io.inc_r) { e0 = io.inc_r[(size_t)g * nh + m]; e1 = io.inc_r[((size_t)G + g) * nh + m]; }
+        }
+    }
+    fill(0, 0, tid, kSweepBlock);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        if (tid >= prod0 && c + 1 < nchunks) fill(c + 1, (c + 1) & 1, tid - prod0, nprod);
+        if (tid < NG) {
+            const double *src = s_ring + (size_t)(c & 1) * C * per_step + (size_t)tid * 6;
+            const int s0 = c * C;
+            const int ns = min(C, J - s0);
+            double *ein = S.si_ein + ((size_t)s0 * NG + tid) * 2;
+            for (int sl = 0; sl < ns; ++sl) {
+                const double *v = src + (size_t)sl * per_step;
+                ein[(size_t)sl * NG * 2 + 0] = e0;
+                ein[(size_t)sl * NG * 2 + 1] = e1;
+                const double n0 = v[0] + v[2] * e0 + v[3] * e1;
+                const double n1 = v[1] + v[4] * e0 + v[5] * e1;
+                e0 = n0;
+                e1 = n1;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -935,9 +994,19 @@ __global__ __launch_bounds__(kBlock) void k_si_flux(Slab S) {
     double dsq = 0.0;
     if (t < total) {
         const int u = t & 3;
-        const double *p = S.psi[cur ^ 1] + (t >> 2) * S.N * 4 + u;
+        const int N = S.N, G = S.G, NG = N * G;
+        const size_t jg = t >> 2;
+        const int g = jg % G, j = jg / G;
+        double *p = S.psi[cur ^ 1] + jg * N * 4 + u;
+        const double *rs = S.si_resp + jg * N * 8 + u;
         double f = 0.0;
-        for (int m = 0; m < S.N; ++m) f += S.w[m] * p[m * 4];
+        for (int m = 0; m < N; ++m) {
+            const int step = S.mu[m] > 0.0 ? j : S.J - 1 - j;
+            const double *ei = S.si_ein + ((size_t)step * NG + g * N + m) * 2;
+            const double x = p[m * 4] + rs[m * 8] * ei[0] + rs[m * 8 + 4] * ei[1];
+            p[m * 4] = x;
+            f += S.w[m] * x;
+        }
         const double f0 = S.phi[cur][t];
         S.phi[cur ^ 1][t] = f;
         dsq = (f - f0) * (f - f0);
@@ -1208,9 +1277,25 @@ hipError_t launch_end(const Slab &S, const StepIO &io, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Steps per LDS chunk of the sweep: two chunks of C x NG x 6 doubles in at
+// most 128 KiB.
+int si_chunk(const Slab &S) {
+    const int NG = S.N * S.G;
+    int C = (int)(131072 / (96 * (size_t)NG));
+    if (C > 256) C = 256;
+    if (C < 1) C = 1;
+    if (C > S.J) C = S.J;
+    return C;
+}
+
 hipError_t launch_si_iteration(const Slab &S, const StepIO &io, hipStream_t st) {
-    const int chains = S.N * S.G;
-    hipLaunchKernelGGL(k_si_sweep, dim3((chains + 63) / 64), dim3(64), 0, st, S, io);
+    const size_t rows = (size_t)S.J * S.G * S.N;
+    hipLaunchKernelGGL(k_si_pre, dim3((unsigned)((rows + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S);
+    const int C = si_chunk(S);
+    const size_t dyn = (size_t)2 * C * S.N * S.G * 6 * 8;
+    hipError_t e = hipFuncSetAttribute((const void *)&k_si_sweep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_si_sweep, dim3(1), dim3(kSweepBlock), dyn, st, S, io, C);
     const size_t tot = (size_t)S.J * S.G * 4;
     hipLaunchKernelGGL(k_si_flux, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S);
     return hipGetLastError();

@@ -230,3 +230,21 @@ def test_kernel_variants_lockstep(name, mode, monkeypatch):
         if tol is not None:
             want = oracle.Oracle(p).run("oci", steps=steps, fixed_iters=K)["phi"]
             assert rel(got, want) <= tol
+
+
+@pytest.mark.parametrize("name", ["regions512_n64", "multigroup128_n256", "G3_n48"])
+def test_autotune_keeps_parity(name):
+    """The autotuner's chosen shape still gives the oracle's lock-step answer."""
+    p, steps = CASES[name]
+    _announce(name, p, "autotune then lock-step")
+    for prec in (B.OCI_FP64, B.OCI_FP32_REFINED):
+        s = B.Solver(p, precision=prec, fixed_iters=6)
+        cfg = s.autotune(iters=4)
+        print("chosen", cfg, flush=True)
+        assert cfg["block"] in (256, 1024) and cfg["workgroups"] >= 1
+        got, infos = s.run(steps=steps)
+        s.close()
+        assert all(i["iterations"] == 6 and i["status"] == 0 for i in infos), infos
+        if prec == B.OCI_FP64:
+            want = oracle.Oracle(p).run("oci", steps=steps, fixed_iters=6)["phi"]
+            assert rel(got, want) <= 1e-12
