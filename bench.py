@@ -2,14 +2,20 @@
 """Benchmark: cell-solves/s and seconds per converged time step at tol 1e-10,
 FP32-refined OCI against FP64 OCI and GPU source iteration, on one MI355X.
 
-Workload (default "regions4096"): the one-group slab of 4096 cells on [0, 64]
-cm in 64 random regions (sigma_t ~ U[0.1, 10], c ~ U[0.5, 0.999], seed 2),
-S16 (cell systems of n = 64), Q = 1 in the first 8 regions, vacuum boundaries,
+Default workload "regions4096": the one-group slab of 4096 cells on [0, 64] cm
+in 64 random regions (sigma_t ~ U[0.1, 10], c ~ U[0.5, 0.999], seed 2), S16
+(cell systems of n = 64), Q = 1 in the first 8 regions, vacuum boundaries,
 zero initial flux, for each time-step size of the sweep {0.1, 0.01, 1e-3,
-1e-4} s.  One benchmark step = one converged time step of every problem of
-the sweep (four OCI time steps).  K steps reproduce K time steps of the
-workload from zero initial flux; setup (assembly + LU + inversion on the
-device) happens before the timed region and is reported separately.
+1e-4} s.  One benchmark step = one converged time step of every problem of the
+sweep (four OCI time steps).  K steps reproduce K time steps of the workload
+from zero initial flux (the state is reset after the W warm-up steps); setup
+(device assembly + LU + inversion, then the launch-shape autotuner) happens
+before the timed region and is reported separately.
+
+Other workloads: "homogeneous64", "multigroup8192", "multigroup16384" (one
+problem each), and "batch64": the 64 uneven slabs advanced together by the
+batched persistent launch with K graph-captured steps, against the same slabs
+solved one after another in FP64.
 
 value = cell-solves / s of the FP32-refined path over the timed region, a
 cell-solve being one cell's 4NG system solved once in one iteration.
@@ -19,8 +25,10 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,8 +37,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-MI355X_HBM_TBS = 8.0          # published HBM3E peak, TB/s
-MI355X_FP32_TFLOPS = 157.3    # published FP32 vector peak
+MI355X_HBM_GBS = 8000.0       # published HBM3E peak, GB/s
 
 
 def parse():
@@ -41,9 +48,10 @@ def parse():
     ap.add_argument("--workload", default="regions4096")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="budget of the CPU-oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--slabs", type=int, default=64, help="batch64: number of slabs")
     return ap.parse_args()
 
 
@@ -56,52 +64,113 @@ def problems(name):
     return p, [p]
 
 
-def run_method(probs, method, precision, K, W_, tol, torch, B, profile=False):
-    """Set up one solver per problem, warm up, reset, then time K steps."""
-    solvers, setup_s = [], []
+def kernel_label(cfg, fp32, np_):
+    t = "float" if fp32 else "double"
+    kind = "k_oci_local" if cfg["local"] else "k_oci_step"
+    return f"{kind}<{t},{np_},{'true' if cfg['resident'] else 'false'},{cfg['block']}>"
+
+
+def run_method(probs, method, precision, K, W_, tol, torch, B, autotune=True):
+    """Set up one solver per problem, tune, warm up, reset, then time K steps."""
+    solvers, setup_s, configs = [], [], []
     for p in probs:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s = B.Solver(p, precision=precision, tol=tol)
         torch.cuda.synchronize()
         setup_s.append(time.perf_counter() - t0)
+        if autotune and method == "oci":
+            s.autotune(8)
+        configs.append(s.config())
         solvers.append(s)
     for s in solvers:
         for _ in range(W_):
             s.step(method)
         s.set_state(None)      # back to zero initial flux and a fresh first iterate
     infos = torch.zeros((K, len(solvers), 32), dtype=torch.uint8, device=solvers[0].dev)
-    if profile:
-        for s in solvers:
-            B.oci_profile_enable(s.h, True)
+    for s in solvers:
+        B.oci_profile_enable(s.h, True)
     fn = B.oci_step if method == "oci" else B.si_step
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
-    t0 = time.perf_counter()
     for k in range(K):
         for i, s in enumerate(solvers):
             fn(s.h, s.q, s.inc_l, s.inc_r, s.phi, None, infos[k, i])
     ev1.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
-    kern = [B.oci_profile_read(s.h) if profile else (0.0, 0) for s in solvers]
+    kern = [B.oci_profile_read(s.h) for s in solvers]
     inf = infos.cpu().numpy()
     dec = [[B.decode_info(inf[k, i]) for i in range(len(solvers))] for k in range(K)]
     for s in solvers:
         s.close()
     its = np.array([[d["iterations"] for d in row] for row in dec])       # [K][problems]
     status = sorted({d["status"] for row in dec for d in row})
-    J = probs[0]["J"]
-    per_dt = []
-    for i, p in enumerate(probs):
-        per_dt.append(dict(dt=p["dt"], setup_s=setup_s[i],
-                           iterations_per_step=float(its[:, i].mean()),
-                           iterations_max=int(its[:, i].max())))
-    return dict(time_s=max(gpu_ms / 1e3, 1e-12), wall_s=wall, iterations=its, J=J,
-                cell_solves=int(its.sum()) * J, per_dt=per_dt, status=status, kernel=kern)
+    cell_solves = int(sum(its[:, i].sum() * p["J"] for i, p in enumerate(probs)))
+    per = [dict(dt=p["dt"], setup_s=setup_s[i], iterations_per_step=float(its[:, i].mean()),
+                iterations_max=int(its[:, i].max())) for i, p in enumerate(probs)]
+    return dict(time_s=max(gpu_ms / 1e3, 1e-12), cell_solves=cell_solves, per=per, status=status,
+                kernel=kern, configs=configs)
+
+
+def summary(r, label, K, keys):
+    """Per-method figures; seconds per converged step per problem come from the
+    iteration-kernel events of that problem."""
+    return dict(cell_solves_per_s=r["cell_solves"] / r["time_s"],
+                s_per_converged_step={k: ms / 1e3 / max(cnt, 1) for (ms, cnt), k in zip(r["kernel"], keys)},
+                iterations_per_step={k: x["iterations_per_step"] for x, k in zip(r["per"], keys)},
+                setup_s={k: round(x["setup_s"], 4) for x, k in zip(r["per"], keys)},
+                timed_region_s=round(r["time_s"], 6), ms_per_bench_step=round(r["time_s"] * 1e3 / K, 4),
+                kernel_ms=round(sum(k[0] for k in r["kernel"]), 3), status=r["status"],
+                launch_shape=r["configs"][0], label=label)
+
+
+def recorded_traffic(label):
+    """HBM bytes per cell-iteration of `label` from the committed PMC summary,
+    valid only while the kernel source is the one the counters were taken on."""
+    src = os.path.join(ROOT, "paper_2503_00264_amd", "csrc", "oci_step.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_regions4096.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source sha256\[:16\]: `([0-9a-f]+)`", text)
+    k = re.search(r"kernel: `([^`]+)`", text)
+    t = re.search(r"HBM bytes per cell-iteration: ([0-9.]+)", text)
+    if not (m and k and t) or m.group(1) != digest or k.group(1) != label:
+        return None
+    return float(t.group(1))
+
+
+def roofline_for(prim, probs, fp32):
+    """Roofline of the dominant kernel (the persistent OCI kernel of the
+    measured path, one launch per time step).  Algorithmic bytes per
+    cell-iteration: the factor stream plus iterate, edge, source and flux
+    traffic, 4 n^2 + 4 n + 128 N G + 64 G (FP32 factors) or
+    8 n^2 + 4 n + 96 N G + 64 G (FP64)."""
+    p = probs[0]
+    N, G = p["N"], p["G"]
+    n = 4 * N * G
+    np_ = 8
+    while np_ < n:
+        np_ *= 2
+    kern_ms = sum(k[0] for k in prim["kernel"])
+    launches = sum(k[1] for k in prim["kernel"])
+    avg_launch_s = kern_ms / 1e3 / max(launches, 1)
+    bpc = (4 * n * n + 4 * n + 128 * N * G + 64 * G) if fp32 else (8 * n * n + 4 * n + 96 * N * G + 64 * G)
+    cpl = prim["cell_solves"] / max(launches, 1)
+    achieved = bpc * cpl / avg_launch_s / 1e9
+    label = kernel_label(prim["configs"][0], fp32, np_)
+    tr = recorded_traffic(label)
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=MI355X_HBM_GBS, unit="GB/s",
+                frac=round(achieved / MI355X_HBM_GBS, 4),
+                traffic=None if tr is None else round(tr * cpl, 1),
+                kernel=label, avg_launch_us=round(avg_launch_s * 1e6, 2),
+                cell_iterations_per_launch=round(cpl, 1), bytes_per_cell_iteration=bpc,
+                flops_per_cell_iteration=2 * n * n,
+                achieved_tflops=round(2 * n * n * cpl / avg_launch_s / 1e12, 3))
 
 
 def cpu_baseline(prob, seconds):
@@ -121,61 +190,116 @@ def cpu_baseline(prob, seconds):
     dt = time.perf_counter() - t0
     return dict(value=its * prob["J"] / dt, unit="cell-solves/s", cores=threads, kind="oracle",
                 sample=f"first {steps} converged time step(s) of the dt={prob['dt']} problem "
-                       f"({its} iterations x {prob['J']} cells, {dt:.1f} s, setup excluded)")
+                       f"(J={prob['J']}, n={4 * prob['N'] * prob['G']}: {its} iterations x {prob['J']} "
+                       f"cells, {dt:.1f} s, setup excluded)")
+
+
+def run_batch(probs, K, W_, tol, torch, B, precision):
+    """The batched launch: K steps captured once into a graph, timed replay."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bs = B.BatchSolver(probs, precision=precision, tol=tol)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    for _ in range(W_):
+        bs.step()
+    for k in range(len(probs)):
+        bs.set_state(k, None)
+    bs.capture(K)
+    bs.stream.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(bs.stream)
+    bs.replay()
+    ev1.record(bs.stream)
+    _, infos = bs.results()
+    ms = ev0.elapsed_time(ev1)
+    geo = bs.geometry()
+    bs.close()
+    # iterations of the last step per slab are in the infos; the total count
+    # of the K steps comes from a second, eager pass with per-step infos
+    return dict(time_s=ms / 1e3, setup_s=setup, infos=infos, geometry=geo)
+
+
+def batch_main(a, torch, B):
+    from paper_2503_00264_amd import workloads as W
+    probs = W.config("batch64", n_slabs=a.slabs, steps=a.steps)
+    K = a.steps
+    # eager pass with per-step infos gives the iteration counts of every step
+    bs = B.BatchSolver(probs, precision=B.OCI_FP32_REFINED, tol=a.tol)
+    its = np.zeros((K, len(probs)), dtype=np.int64)
+    status = set()
+    for k in range(K):
+        bs.step()
+        _, infos = bs.results()
+        its[k] = [i["iterations"] for i in infos]
+        status |= {i["status"] for i in infos}
+    bs.close()
+    torch.cuda.empty_cache()
+    r = run_batch(probs, K, a.warmup, a.tol, torch, B, B.OCI_FP32_REFINED)
+    J = np.array([p["J"] for p in probs])
+    cell_solves = int((its * J[None, :]).sum())
+    value = cell_solves / r["time_s"]
+    out = {
+        "metric": "cell-solves/s and s per converged step: FP32-refined vs FP64 OCI vs SI @1e-10",
+        "value": round(value, 1), "unit": "cell-solves/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
+        "ms_per_step": round(r["time_s"] * 1e3 / K, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 solve + f64 residual/norm/update",
+        "data": "synthetic (seeded generator; no external data)",
+        "config": {"workload": f"batch64: {len(probs)} slabs, J in [{J.min()}, {J.max()}], "
+                               f"n in {sorted({4 * p['N'] * p['G'] for p in probs})}, dt 1e-3, "
+                               f"{K} graph-captured batched steps", "slabs": len(probs),
+                   "cells": int(J.sum())},
+        "batch": {"setup_s": round(r["setup_s"], 3), "workgroups": r["geometry"][0],
+                  "iterations_per_step_max": int(its.max()), "status": sorted(status)},
+    }
+    if not a.no_comparators:
+        t_seq = 0.0
+        cs_seq = 0
+        for p in probs:
+            s = B.Solver(p, precision=B.OCI_FP64, tol=a.tol)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            infos = []
+            for _ in range(K):
+                s.step("oci")
+                infos.append(s.info.clone())
+            ev1.record()
+            torch.cuda.synchronize()
+            t_seq += ev0.elapsed_time(ev1) / 1e3
+            cs_seq += sum(B.decode_info(i.cpu().numpy())["iterations"] for i in infos) * p["J"]
+            s.close()
+            torch.cuda.empty_cache()
+        out["comparison"] = {"fp64_sequential": {"time_s": round(t_seq, 4),
+                                                 "cell_solves_per_s": cs_seq / t_seq,
+                                                 "speedup_of_batched_fp32": round(t_seq / r["time_s"], 3)}}
+    print(json.dumps(out), flush=True)
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": a.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
     from paper_2503_00264_amd import binding as B
     torch.cuda.set_device(0)
+    if a.workload == "batch64":
+        batch_main(a, torch, B)
+        return
     base, probs = problems(a.workload)
     N, G, J = base["N"], base["G"], base["J"]
     n = 4 * N * G
-
-    prim = run_method(probs, "oci", B.OCI_FP32_REFINED, a.steps, a.warmup, a.tol, torch, B, profile=True)
+    keys = [str(p["dt"]) for p in probs]
+    tune = not a.no_autotune
+    prim = run_method(probs, "oci", B.OCI_FP32_REFINED, a.steps, a.warmup, a.tol, torch, B, tune)
     comp = {}
     if not a.no_comparators:
-        comp["fp64"] = run_method(probs, "oci", B.OCI_FP64, a.steps, a.warmup, a.tol, torch, B, profile=True)
-        comp["si"] = run_method(probs, "si", B.OCI_FP64, a.steps, a.warmup, a.tol, torch, B, profile=True)
-
+        comp["fp64"] = run_method(probs, "oci", B.OCI_FP64, a.steps, a.warmup, a.tol, torch, B, tune)
+        comp["si"] = run_method(probs, "si", B.OCI_FP64, a.steps, a.warmup, a.tol, torch, B, False)
     value = prim["cell_solves"] / prim["time_s"]
-    ms_per_step = prim["time_s"] * 1e3 / a.steps
-
-    # roofline of the dominant kernel: the persistent OCI kernel of the
-    # refined path, one launch per time step.  Algorithmic bytes per
-    # cell-iteration (factor stream + iterate/edge/source/flux traffic):
-    #   4 n^2 + 4 n + 128 N G + 64 G
-    kern_ms = sum(k[0] for k in prim["kernel"])
-    launches = sum(k[1] for k in prim["kernel"])
-    avg_launch_s = kern_ms / 1e3 / max(launches, 1)
-    bytes_per_ci = 4 * n * n + 4 * n + 128 * N * G + 64 * G
-    cell_iters_per_launch = prim["cell_solves"] / max(launches, 1)
-    achieved = bytes_per_ci * cell_iters_per_launch / avg_launch_s / 1e9
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=MI355X_HBM_TBS * 1e3, unit="GB/s",
-                    frac=round(achieved / (MI355X_HBM_TBS * 1e3), 4), traffic=None,
-                    kernel="k_oci_step<float,64,resident>",
-                    avg_launch_us=round(avg_launch_s * 1e6, 2),
-                    cell_iterations_per_launch=round(cell_iters_per_launch, 1),
-                    bytes_per_cell_iteration=bytes_per_ci,
-                    flops_per_cell_iteration=2 * n * n,
-                    achieved_tflops_fp32=round(2 * n * n * cell_iters_per_launch / avg_launch_s / 1e12, 3))
-
-    def summary(r, label):
-        """Per-method figures; seconds per converged step per dt come from the
-        iteration-kernel events of that dt's problem."""
-        return dict(cell_solves_per_s=r["cell_solves"] / r["time_s"],
-                    s_per_converged_step={str(x["dt"]): ms / 1e3 / max(cnt, 1)
-                                          for (ms, cnt), x in zip(r["kernel"], r["per_dt"])},
-                    iterations_per_step={str(x["dt"]): x["iterations_per_step"] for x in r["per_dt"]},
-                    setup_s={str(x["dt"]): round(x["setup_s"], 4) for x in r["per_dt"]},
-                    timed_region_s=round(r["time_s"], 6),
-                    kernel_ms=round(sum(k[0] for k in r["kernel"]), 3), status=r["status"], label=label)
-
     out = {
         "metric": "cell-solves/s and s per converged step: FP32-refined vs FP64 OCI vs SI @1e-10",
         "value": round(value, 1),
@@ -183,21 +307,23 @@ def main():
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(prim["time_s"] * 1e3 / a.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 solve + f64 residual/norm/update",
         "data": "synthetic (seeded generator; no external data)",
-        "config": {"workload": f"{a.workload}: J={J} N={N} G={G} n={n}, dt sweep "
-                               f"{[p['dt'] for p in probs]}, tol {a.tol}, one step = one time step "
-                               f"of each dt", "J": J, "N": N, "G": G, "n": n,
-                   "dts": [p["dt"] for p in probs], "tol": a.tol},
-        "roofline": roofline,
-        "comparison": {"fp32_refined": summary(prim, "FP32 LU+inverse, FP64 residual refinement")},
+        "config": {"workload": f"{a.workload}: J={J} N={N} G={G} n={n}, dt {keys}, tol {a.tol}, "
+                               f"one step = one converged time step of each dt",
+                   "J": J, "N": N, "G": G, "n": n, "dts": [p["dt"] for p in probs], "tol": a.tol},
+        "roofline": roofline_for(prim, probs, True),
+        "comparison": {"fp32_refined": summary(prim, "FP32 LU+inverse, FP64 residual refinement", a.steps, keys)},
     }
+    labels = {"fp64": "FP64 LU+inverse OCI", "si": "FP64 source iteration sweep"}
     for k, r in comp.items():
-        out["comparison"][k] = summary(r, {"fp64": "FP64 LU+inverse OCI", "si": "FP64 source iteration sweep"}[k])
+        out["comparison"][k] = summary(r, labels[k], a.steps, keys)
+    if "fp64" in comp:
+        out["comparison"]["fp64"]["roofline"] = roofline_for(comp["fp64"], probs, False)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs[0], a.cpu_seconds)
     print(json.dumps(out), flush=True)
