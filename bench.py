@@ -201,8 +201,9 @@ def run_batch(probs, K, W_, tol, torch, B, precision):
     bs = B.BatchSolver(probs, precision=precision, tol=tol)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
-    for _ in range(W_):
+    for _ in range(max(W_, 1)):
         bs.step()
+    bs.rebalance()             # workgroups per slab from the measured iteration counts
     for k in range(len(probs)):
         bs.set_state(k, None)
     bs.capture(K)
@@ -227,6 +228,10 @@ def batch_main(a, torch, B):
     K = a.steps
     # eager pass with per-step infos gives the iteration counts of every step
     bs = B.BatchSolver(probs, precision=B.OCI_FP32_REFINED, tol=a.tol)
+    bs.step()
+    bs.rebalance()
+    for k in range(len(probs)):
+        bs.set_state(k, None)
     its = np.zeros((K, len(probs)), dtype=np.int64)
     status = set()
     for k in range(K):

@@ -228,6 +228,12 @@ int oci_batch_replay(oci_batch *b);
 int oci_batch_set_state(oci_batch *b, int32_t k, const double *psi_prev_dev);
 int oci_batch_get_state(const oci_batch *b, int32_t k, double *psi_prev_dev);
 
+/* Batch autotuning: re-size every slab's block of workgroups in proportion
+ * to J x (4NG)^2 x (iterations of its last step, read from the bound info
+ * array), so slabs that converge slowly get more of the launch.  Synchronises
+ * the stream; a captured graph is discarded (capture again afterwards). */
+int oci_batch_rebalance(oci_batch *b);
+
 /* Launch geometry: total workgroups and, if nwg_per_slab is not NULL, the
  * workgroups of each slab ([nslab]). */
 int oci_batch_info(const oci_batch *b, int32_t *nwg_total, int32_t *nwg_per_slab);

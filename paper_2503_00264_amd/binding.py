@@ -28,7 +28,7 @@ EXPORTS = ("oci_workspace_bytes", "oci_setup", "oci_set_state", "oci_get_state",
            "oci_step", "si_step", "oci_profile_enable", "oci_profile_read",
            "oci_autotune", "oci_get_config", "oci_destroy", "oci_batch_workspace_bytes", "oci_batch_setup", "oci_batch_bind",
            "oci_batch_step", "oci_batch_capture", "oci_batch_replay", "oci_batch_set_state",
-           "oci_batch_get_state", "oci_batch_info", "oci_batch_destroy", "oci_status_string")
+           "oci_batch_get_state", "oci_batch_rebalance", "oci_batch_info", "oci_batch_destroy", "oci_status_string")
 
 
 class OciError(RuntimeError):
@@ -84,6 +84,7 @@ def lib():
         L.oci_batch_set_state.argtypes = [vp, i32, vp]
         L.oci_batch_get_state.argtypes = [vp, i32, vp]
         L.oci_batch_info.argtypes = [vp, vp, vp]
+        L.oci_batch_rebalance.argtypes = [vp]
         L.oci_batch_destroy.argtypes = [vp]
         L.oci_status_string.argtypes = [i32]
         L.oci_status_string.restype = C.c_char_p
@@ -247,6 +248,10 @@ def oci_batch_info(b, nslab):
     per = (C.c_int32 * nslab)()
     _check("oci_batch_info", lib().oci_batch_info(b, C.byref(tot), per))
     return tot.value, list(per)
+
+
+def oci_batch_rebalance(b):
+    _check("oci_batch_rebalance", lib().oci_batch_rebalance(b))
 
 
 def oci_batch_destroy(b):
@@ -419,6 +424,10 @@ class BatchSolver:
 
     def geometry(self):
         return oci_batch_info(self.b, len(self.probs))
+
+    def rebalance(self):
+        """Re-size the slabs' workgroup blocks from the last step's iterations."""
+        oci_batch_rebalance(self.b)
 
     def close(self):
         if self.b is not None:

@@ -553,7 +553,9 @@ struct oci_batch {
     std::vector<BatchEntry> tab;   // host copy of the device table
     BatchEntry *d_tab;             // in the workspace
     int nwg;                       // workgroups of the batched launch
+    int occ;                       // co-resident batch workgroups per CU
     bool bound;
+    oci_step_info *info_dev;       // bound per-slab results
     hipGraphExec_t graph;
     int graph_steps;
 };
@@ -583,6 +585,51 @@ extern "C" int oci_batch_destroy(oci_batch *b) {
     return OCI_OK;
 }
 
+// Workgroups per slab in proportion to `weight`, at least one, at most the
+// slab's tile count, all co-resident (at most occupancy x CUs in total).
+static int batch_allocate(oci_batch *b, const std::vector<double> &weight) {
+    const int nslab = b->nslab;
+    const int num_cu = b->slabs[0]->num_cu;
+    long cap = (long)b->occ * num_cu;
+    if (cap > (long)num_cu * 8) cap = (long)num_cu * 8;
+    if (nslab > cap) return OCI_ERR_UNSUPPORTED;
+    const int bs = batch_block();
+    std::vector<long> ntile(nslab), alloc(nslab);
+    double wsum = 0.0;
+    for (int k = 0; k < nslab; ++k) {
+        const oci_handle *h = b->slabs[k];
+        const int rpt = h->np > bs ? h->np / bs : 1;
+        const int cpt = bs / (h->np / rpt);
+        ntile[k] = (h->d.J + cpt - 1) / cpt;
+        wsum += weight[k];
+    }
+    long used = 0;
+    for (int k = 0; k < nslab; ++k) {
+        long a = (long)(weight[k] / wsum * (double)cap);
+        if (a < 1) a = 1;
+        if (a > ntile[k]) a = ntile[k];
+        alloc[k] = a;
+        used += a;
+    }
+    while (used > cap) {   // trim the largest allocations
+        int kmax = 0;
+        for (int k = 1; k < nslab; ++k) if (alloc[k] > alloc[kmax]) kmax = k;
+        --alloc[kmax];
+        --used;
+    }
+    int wg0 = 0;
+    for (int k = 0; k < nslab; ++k) {
+        BatchEntry &e = b->tab[k];
+        e.S.bar_groups = (int)((alloc[k] + e.S.bar_gsz - 1) / e.S.bar_gsz);
+        e.ntiles = (int)ntile[k];
+        e.wg0 = wg0;
+        e.nwg = (int)alloc[k];
+        wg0 += e.nwg;
+    }
+    b->nwg = wg0;
+    return OCI_OK;
+}
+
 extern "C" int oci_batch_setup(int32_t nslab, const oci_desc *descs, void *workspace_dev, size_t workspace_bytes,
                                void *stream, oci_batch **out) {
     if (!out) return OCI_ERR_INVALID;
@@ -609,53 +656,21 @@ extern "C" int oci_batch_setup(int32_t nslab, const oci_desc *descs, void *works
         b->slabs.push_back(h);
         off += align256(bk);
     }
-    // workgroups: proportional to each slab's factor bytes per iteration
-    // (J np^2), at least one, at most its tile count, all co-resident
     int occ = 0;
     if (batch_occupancy(b->fp32, &occ) != hipSuccess || occ < 1) { oci_batch_destroy(b); return OCI_ERR_HIP; }
-    const int num_cu = b->slabs[0]->num_cu;
-    long cap = (long)occ * num_cu;
-    if (cap > (long)num_cu * 8) cap = (long)num_cu * 8;
-    if (nslab > cap) { oci_batch_destroy(b); return OCI_ERR_UNSUPPORTED; }
-    const int bs = batch_block();
-    std::vector<long> ntile(nslab), alloc(nslab);
-    double wsum = 0.0;
+    b->occ = occ;
+    b->tab.resize(nslab);
+    for (int k = 0; k < nslab; ++k) {
+        memset(&b->tab[k], 0, sizeof(BatchEntry));
+        b->tab[k].S = b->slabs[k]->S;
+    }
     std::vector<double> wgt(nslab);
     for (int k = 0; k < nslab; ++k) {
         const oci_handle *h = b->slabs[k];
-        const int rpt = h->np > bs ? h->np / bs : 1;
-        const int cpt = bs / (h->np / rpt);
-        ntile[k] = (h->d.J + cpt - 1) / cpt;
-        wgt[k] = (double)h->d.J * h->np * h->np;
-        wsum += wgt[k];
+        wgt[k] = (double)h->d.J * h->np * h->np;     // factor bytes per iteration
     }
-    long used = 0;
-    for (int k = 0; k < nslab; ++k) {
-        long a = (long)(wgt[k] / wsum * (double)cap);
-        if (a < 1) a = 1;
-        if (a > ntile[k]) a = ntile[k];
-        alloc[k] = a;
-        used += a;
-    }
-    while (used > cap) {   // trim the largest allocations
-        int kmax = 0;
-        for (int k = 1; k < nslab; ++k) if (alloc[k] > alloc[kmax]) kmax = k;
-        --alloc[kmax];
-        --used;
-    }
-    b->tab.resize(nslab);
-    int wg0 = 0;
-    for (int k = 0; k < nslab; ++k) {
-        BatchEntry &e = b->tab[k];
-        memset(&e, 0, sizeof(e));
-        e.S = b->slabs[k]->S;
-        e.S.bar_groups = (int)((alloc[k] + e.S.bar_gsz - 1) / e.S.bar_gsz);
-        e.ntiles = (int)ntile[k];
-        e.wg0 = wg0;
-        e.nwg = (int)alloc[k];
-        wg0 += e.nwg;
-    }
-    b->nwg = wg0;
+    rc = batch_allocate(b, wgt);
+    if (rc) { oci_batch_destroy(b); return rc; }
     b->bound = false;
     *out = b;
     return OCI_OK;
@@ -675,6 +690,7 @@ extern "C" int oci_batch_bind(oci_batch *b, const double *const *q_dev, const do
         io.psi_out = nullptr;
         io.info = info_dev + k;
     }
+    b->info_dev = info_dev;
     if (hipMemcpyAsync(b->d_tab, b->tab.data(), sizeof(BatchEntry) * b->nslab, hipMemcpyHostToDevice, b->st) !=
         hipSuccess)
         return OCI_ERR_HIP;
@@ -727,6 +743,24 @@ extern "C" int oci_batch_set_state(oci_batch *b, int32_t k, const double *psi_pr
 extern "C" int oci_batch_get_state(const oci_batch *b, int32_t k, double *psi_prev_dev) {
     if (!b || k < 0 || k >= b->nslab) return OCI_ERR_INVALID;
     return oci_get_state(b->slabs[k], psi_prev_dev);
+}
+
+extern "C" int oci_batch_rebalance(oci_batch *b) {
+    if (!b || !b->bound) return OCI_ERR_INVALID;
+    std::vector<oci_step_info> info(b->nslab);
+    HIPCHECK(hipStreamSynchronize(b->st));
+    HIPCHECK(hipMemcpy(info.data(), b->info_dev, sizeof(oci_step_info) * b->nslab, hipMemcpyDeviceToHost));
+    std::vector<double> wgt(b->nslab);
+    for (int k = 0; k < b->nslab; ++k) {
+        const oci_handle *h = b->slabs[k];
+        const int its = info[k].iterations > 0 ? info[k].iterations : 1;
+        wgt[k] = (double)h->d.J * h->np * h->np * its;
+    }
+    const int rc = batch_allocate(b, wgt);
+    if (rc) return rc;
+    HIPCHECK(hipMemcpy(b->d_tab, b->tab.data(), sizeof(BatchEntry) * b->nslab, hipMemcpyHostToDevice));
+    if (b->graph) { (void)hipGraphExecDestroy(b->graph); b->graph = nullptr; }
+    return OCI_OK;
 }
 
 extern "C" int oci_batch_info(const oci_batch *b, int32_t *nwg_total, int32_t *nwg_per_slab) {

@@ -108,3 +108,26 @@ def test_batch_state_replacement():
     bs.close()
     want = oracle.Oracle(probs[k]).run("oci", steps=1, fixed_iters=4, psi_init=psi0)["phi"][0]
     assert rel(phis[k], want) <= 1e-12
+
+
+def test_batch_rebalance_keeps_results():
+    probs = [p for p in small_batch(seed=9) if 4 * p["N"] * p["G"] <= 512]
+    _announce(probs, "rebalance, then step and capture")
+    a = B.BatchSolver(probs, precision=B.OCI_FP64, fixed_iters=5)
+    b = B.BatchSolver(probs, precision=B.OCI_FP64, fixed_iters=5)
+    a.step()
+    b.step()
+    before = b.geometry()
+    b.rebalance()
+    after = b.geometry()
+    assert sum(after[1]) == after[0] and min(after[1]) >= 1
+    a.step()
+    b.capture(1)
+    b.replay()
+    pa, _ = a.results()
+    pb, ib = b.results()
+    a.close()
+    b.close()
+    assert all(i["iterations"] == 5 for i in ib)
+    for k in range(len(probs)):
+        assert rel(pb[k], pa[k]) <= 1e-12, (k, before, after)
