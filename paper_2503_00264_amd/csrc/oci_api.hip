@@ -15,7 +15,7 @@
 
 namespace oci {
 hipError_t launch_setup(const Slab &S, bool fp32, hipStream_t st);
-hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, hipStream_t st);
+hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, hipStream_t st, int local_nwg);
 hipError_t launch_end(const Slab &S, const StepIO &io, hipStream_t st);
 hipError_t launch_oci_step(const Slab &S, const StepIO &io, bool fp32, int np, bool res, int bs, int nwg, int ntiles,
                            hipStream_t st, bool cooperative);
@@ -48,6 +48,7 @@ struct oci_handle {
     size_t ws_bytes;
     int nwg, ntiles;       // OCI persistent launch geometry
     int block;             // threads per workgroup of the OCI kernel
+    int max_wg;            // cap on its workgroups (0: none; testing override)
     bool resident;
     bool local;            // workgroup-local kernel (iterate kept in LDS)
     size_t dyn_lds;        // its dynamic LDS bytes
@@ -214,7 +215,8 @@ static int configure(oci_handle *h, int block, bool allow_local, bool allow_res,
     const int tpc = h->np / rpt;
     const int cpt = block / tpc;
     const long ntiles = (h->d.J + cpt - 1) / cpt;
-    const long wg_cap = (long)num_cu * 8;  // partial-sum and exchange slots in the workspace
+    long wg_cap = (long)num_cu * 8;  // partial-sum and exchange slots in the workspace
+    if (h->max_wg > 0 && h->max_wg < wg_cap) wg_cap = h->max_wg;
     int occ_res = 0, occ = 0;
     if (oci_occupancy(h->fp32, h->np, false, block, &occ) != hipSuccess || occ < 1) return OCI_ERR_HIP;
     bool local = false, res = false;
@@ -363,7 +365,12 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
     if (c.singular) { oci_destroy(h); return OCI_ERR_SINGULAR; }
 
     // persistent launch geometry; environment overrides: OCI_BLOCK (256 or
-    // 1024), OCI_MODE=global, OCI_NO_RESIDENT=1 (OCI_BAR_GROUP read above)
+    // 1024), OCI_MODE=global, OCI_NO_RESIDENT=1, OCI_MAX_WG (a cap on the
+    // workgroups, so that each owns several tiles; OCI_BAR_GROUP read above)
+    if (const char *env = getenv("OCI_MAX_WG")) {
+        const int w = atoi(env);
+        if (w >= 1) h->max_wg = w;
+    }
     int block = 1024;
     if (const char *env = getenv("OCI_BLOCK")) {
         const int b = atoi(env);
@@ -406,7 +413,7 @@ extern "C" int oci_step(oci_handle *h, const double *q_dev, const double *inc_le
     int rc = check_step_args(h, phi_out_dev, info_dev);
     if (rc) return rc;
     StepIO io{q_dev, inc_left_dev, inc_right_dev, phi_out_dev, psi_out_dev, info_dev};
-    HIPCHECK(launch_begin(h->S, io, h->need_broadcast, h->st));
+    HIPCHECK(launch_begin(h->S, io, h->need_broadcast, h->st, h->local ? h->nwg : 0));
     h->need_broadcast = false;
     hipEvent_t e0 = h->profiling ? prof_event(h) : nullptr, e1 = h->profiling ? prof_event(h) : nullptr;
     if (e0) HIPCHECK(hipEventRecord(e0, h->st));
@@ -424,7 +431,7 @@ extern "C" int si_step(oci_handle *h, const double *q_dev, const double *inc_lef
     int rc = check_step_args(h, phi_out_dev, info_dev);
     if (rc) return rc;
     StepIO io{q_dev, inc_left_dev, inc_right_dev, phi_out_dev, psi_out_dev, info_dev};
-    HIPCHECK(launch_begin(h->S, io, h->need_broadcast, h->st));
+    HIPCHECK(launch_begin(h->S, io, h->need_broadcast, h->st, 0));
     h->need_broadcast = false;
     // the iterations stop themselves on the device; the host only polls the
     // done flag between growing batches of launches
@@ -498,7 +505,7 @@ extern "C" int oci_autotune(oci_handle *h, int32_t iters, int32_t *config) {
         float ms = 0.f;
         for (int rep = 0; rep < 2 && rc == OCI_OK; ++rep) {   // first run warms up
             if (oci_set_state(h, nullptr) != OCI_OK) { rc = OCI_ERR_HIP; break; }
-            if (launch_begin(h->S, io, true, h->st) != hipSuccess) { rc = OCI_ERR_HIP; break; }
+            if (launch_begin(h->S, io, true, h->st, h->local ? h->nwg : 0) != hipSuccess) { rc = OCI_ERR_HIP; break; }
             h->need_broadcast = false;
             if (hipEventRecord(e0, h->st) != hipSuccess) { rc = OCI_ERR_HIP; break; }
             hipError_t e = h->local ? launch_oci_local(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg,

@@ -16,6 +16,15 @@ constexpr int kBlock = 256;
 // kBarGroup before one leader per group arrives at the top counter.
 constexpr int kBarStride = 32;
 constexpr int kBarGroup = 16;
+// Hand-off slots of the workgroup-local kernel.  An exchange slot holding
+// kEdgeEmpty has been consumed (a NaN payload no arithmetic produces; a value
+// with this bit pattern is replaced by the default NaN before it is
+// published).  A partial-sum slot holds the bits of a non-negative double
+// whose low kPartTagBits mantissa bits carry the iteration number modulo
+// 2^kPartTagBits; kPartEmpty (sign bit set) never matches a tag.
+constexpr uint64_t kEdgeEmpty = 0xFFF4C0DE5E4714E1ull;
+constexpr uint64_t kPartEmpty = ~0ull;
+constexpr int kPartTagBits = 4;
 
 // Control block of one slab problem, in the workspace.  Written by the step
 // kernels only; the host reads `done` to learn that a step has stopped.

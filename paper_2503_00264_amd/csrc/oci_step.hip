@@ -15,9 +15,11 @@
 //      they fit);
 //   4. writes Psi^(l+1), the scalar flux phi = sum_m w_m psi_m (eq. si_sf) and
 //      its squared change into a per-workgroup partial sum;
-//   5. meets every workgroup at a grid barrier; the last to arrive sums the
-//      partials in a fixed order and applies the stopping rule, so the whole
-//      decision stays on the device and repeats bit for bit.
+//   5. takes the stopping decision on the device from the per-workgroup
+//      partials, summed in a fixed order by every workgroup, so it repeats
+//      bit for bit: after a grid barrier (global-memory kernels), or, in the
+//      workgroup-local kernel, from partials tagged with their iteration
+//      while the next iteration's solve is already under way.
 // SI (Appendix A, Algorithm 1): one kernel sweeps all (group, angle) chains
 // cell by cell with the lagged scattering source, a second forms phi and the
 // norm and takes the decision (last-block reduction).
@@ -102,9 +104,14 @@ __device__ inline void phi0_elem(const Slab &S, size_t t) {
     for (int m = 0; m < S.N; ++m) s += S.w[m] * p[m * 4];
     S.phi[b][t] = s;
 }
-__global__ __launch_bounds__(kBlock) void k_phi0(Slab S) {
+// Also empties the hand-off slots of a workgroup-local launch of nwg
+// workgroups that follows (nwg = 0: none).
+__global__ __launch_bounds__(kBlock) void k_phi0(Slab S, int nwg) {
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < (size_t)S.J * S.G * 4) phi0_elem(S, t);
+    const size_t nex = (size_t)4 * nwg * S.N * S.G;
+    if (t < nex) reinterpret_cast<uint64_t *>(S.exch)[t] = kEdgeEmpty;
+    if (t < (size_t)2 * nwg) reinterpret_cast<uint64_t *>(S.partials)[t] = kPartEmpty;
 }
 
 // psi of the first iterate from the state (both time levels).
@@ -490,70 +497,77 @@ void k_oci_step(Slab S, StepIO io, int ntiles) {
 
 // Relaxed agent-scope accesses: coherent across the XCDs without any L2
 // writeback or invalidate.  Only the data that crosses workgroups inside a
-// launch (boundary edges, partial sums, barrier counters) goes through them.
-__device__ inline void st_agent(double *p, double v) {
+// launch (boundary edges and partial sums) goes through them.
+__device__ inline uint64_t ld_bits(const uint64_t *p) {
+    return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_bits(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline double ld_agent(const double *p) {
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+// Edge hand-off between neighbouring workgroups: the producer stores the
+// value into an empty slot; the consumer waits until the slot is no longer
+// empty, takes the value and marks the slot empty again.  The wait is
+// bounded: on expiry *bad is raised and the value is NaN.
+__device__ inline void put_edge(uint64_t *slot, double v) {
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    if (b == kEdgeEmpty) b = 0x7FF8000000000000ull;
+    st_bits(slot, b);
+}
+__device__ inline double take_edge(uint64_t *slot, int *bad) {
+    uint64_t b = ld_bits(slot);
+    long spins = 0;
+#pragma clang loop unroll(disable)
+    while (b == kEdgeEmpty) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) { *bad = 1; break; }
+        b = ld_bits(slot);
+    }
+    st_bits(slot, kEdgeEmpty);
+    return __longlong_as_double((long long)b);
 }
 
-// Grid barrier for the workgroup-local kernel: every wave first waits for its
-// own agent-scope stores to complete (s_waitcnt), so when the counters reach
-// their target every published value is at the coherence point; arrivals and
-// the wait are relaxed, and no cache maintenance is issued.  Then each
-// workgroup sums the published partials of iteration l in a fixed order.
+// Partial sums carry the iteration that produced them in their lowest
+// mantissa bits, so a reader recognises the value it waits for by its tag
+// alone (no counter).  Clearing those bits on the way out keeps an exact zero
+// exactly zero.
+constexpr uint64_t kTagMask = (1ull << kPartTagBits) - 1;
+__device__ inline uint64_t part_encode(double v, int l) {
+    const uint64_t b = (uint64_t)__double_as_longlong(fabs(v));
+    return (b & ~kTagMask) | ((uint64_t)l & kTagMask);
+}
+__device__ inline bool part_ready(uint64_t b, int l) {
+    return (b >> 63) == 0 && (b & kTagMask) == ((uint64_t)l & kTagMask);
+}
+__device__ inline double part_value(uint64_t b) { return __longlong_as_double((long long)(b & ~kTagMask)); }
+
+// Sum over the workgroup in a fixed order, returned to every thread.
 template <int BS>
-__device__ inline bool grid_sync_local(const Slab &S, unsigned nwg, int l, double wg_sum, int *s_flag,
-                                       double *s_tmp, double *total) {
-    double *part = S.partials + (size_t)(l & 1) * nwg;
-    if (threadIdx.x == 0) st_agent(part + blockIdx.x, wg_sum);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+__device__ inline double block_sum_all(double v, double *s_tmp) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) s_tmp[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned gsz_all = (unsigned)S.bar_gsz;
-        const unsigned grp = blockIdx.x / gsz_all;
-        const unsigned ngrp = (nwg + gsz_all - 1) / gsz_all;
-        const unsigned gsz = (grp + 1 == ngrp) ? nwg - grp * gsz_all : gsz_all;
-        const uint64_t round = (uint64_t)l + 1;
-        uint64_t *gc = S.bar + (size_t)(2 + grp) * kBarStride;
-        const uint64_t og = __hip_atomic_fetch_add(gc, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (og + 1 == round * gsz) {
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            (void)__hip_atomic_fetch_add(S.bar, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        int bad = 0;
-        long spins = 0;
-        while (__hip_atomic_load(S.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round * ngrp) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) {
-                __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                bad = 1;
-                break;
-            }
-        }
-        asm volatile("" ::: "memory");
-        s_flag[2] = bad;
-    }
-    __syncthreads();
-    double v = 0.0;
-    for (unsigned k = threadIdx.x; k < nwg; k += BS) v += ld_agent(part + k);
-    v = block_sum_t<BS>(v, s_tmp);
-    if (threadIdx.x == 0) s_tmp[BS / 64] = v;
-    __syncthreads();
-    *total = s_tmp[BS / 64];
-    return s_flag[2] == 0;
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < BS / 64; ++w) t += s_tmp[w];
+    return t;
 }
 
 // Workgroup-local persistent OCI kernel.  Each workgroup owns the contiguous
 // cells [c0, c1) for the whole step and keeps their iterate Psi and scalar
 // flux phi in LDS (dynamic shared memory: [cells][n] Psi, [cells][4G] phi,
 // then per internal tile boundary a snapshot of the 2NG edge values that
-// cross it).  Only the edges at the two ends of the range cross workgroups:
-// they are published each iteration into the exchange buffer with agent-scope
-// stores and read by the neighbour with agent-scope loads after the barrier.
-// Iterate 0's neighbour edges come from global memory (written by earlier
-// launches).  At the end the final Psi and phi are written to global memory.
+// cross it).  Only the edges at the two ends of the range cross workgroups,
+// handed to the neighbour through single-use slots (put_edge / take_edge);
+// iterate 0's neighbour edges come from global memory (written by earlier
+// launches).  There is no grid barrier: a workgroup waits only for its two
+// neighbours' edges, and for the tagged partial sums of the previous
+// iteration, which it needs for the stopping decision.  The slots of an
+// iteration's partials are reused two iterations later, and a workgroup can
+// only get there after every workgroup has published the partial of the
+// iteration in between, which it does after its reads (and after the slots
+// it emptied are stored), so no slot is overwritten while still needed.  At
+// the end the final Psi and phi are written to global memory.
 // Template parameters as k_oci_step.
 template <typename T, int NP, bool RES, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
@@ -576,7 +590,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     __shared__ double s_mu[NP / 4], s_w[NP / 4];
     __shared__ double s_tmp[BS / 64 + 1];
     __shared__ double s_max[BS / 64];
-    __shared__ int s_flag[4];
+    __shared__ double s_part[BS / 64];
 
     const int tid = threadIdx.x;
     const int cl = tid / TPC;
@@ -584,8 +598,9 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     const int J = S.J, N = S.N, G = S.G, n = S.n, nh = S.N / 2, NG = S.N * S.G;
     const unsigned nwg = gridDim.x;
     const int wg = blockIdx.x;
-    const int tile0 = (int)(((long)ntiles * wg) / nwg);
-    const int tile1 = (int)(((long)ntiles * (wg + 1)) / nwg);
+    // register-resident rows: one tile per workgroup (launched with nwg = ntiles)
+    const int tile0 = RES ? wg : (int)(((long)ntiles * wg) / nwg);
+    const int tile1 = RES ? wg + 1 : (int)(((long)ntiles * (wg + 1)) / nwg);
     const int ntw = tile1 - tile0;
     const int c0 = tile0 * CPT;
     const int c1 = min(tile1 * CPT, J);
@@ -596,8 +611,9 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     // exchange buffer [2 parity][nwg][2 side][2 lev][G][nh]; side 0: my first
     // cell's L corners of mu<0 angles, side 1: my last cell's R corners of mu>0
     const size_t exw = (size_t)2 * 2 * G * nh;
-    auto exq = [&](int par, int w, int side, int lev, int g, int mm) -> double * {
-        return S.exch + (((size_t)par * nwg + w) * 2 + side) * (exw / 2) + ((size_t)lev * G + g) * nh + mm;
+    uint64_t *exch_bits = reinterpret_cast<uint64_t *>(S.exch);
+    auto exq = [&](int par, int w, int side, int lev, int g, int mm) -> uint64_t * {
+        return exch_bits + (((size_t)par * nwg + w) * 2 + side) * (exw / 2) + ((size_t)lev * G + g) * nh + mm;
     };
 
     for (int m = tid; m < N; m += BS) { s_mu[m] = S.mu[m]; s_w[m] = S.w[m]; }
@@ -635,24 +651,36 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
         __syncthreads();
     }
 
+    // Iteration l forms Psi^(l+1).  Its first tile computes the new values
+    // (steps 1-3) before the decision on iteration l - 1 is known; the
+    // decision is taken before anything in LDS is overwritten, so on a stop
+    // LDS still holds the final iterate.
+    constexpr bool WAVE_CELL = TPC <= 64;   // a cell's rows lie in one wave
+    const bool tree_phi = WAVE_CELL && (N & (N - 1)) == 0;
+    uint64_t *part_bits = reinterpret_cast<uint64_t *>(S.partials);
     double e_prev = __builtin_nan("");
     for (int l = 0;; ++l) {
         const int cur = (base + l) & 1;
         const double *__restrict__ psi_g = S.psi[cur];   // global iterate: only read at l = 0
-        double wg_sum = 0.0;
+        const uint64_t *part_prev = part_bits + (size_t)((l + 1) & 1) * nwg;   // partials of iteration l - 1
+        const int par = (l + 1) & 1;                     // exchange parity this iteration publishes
+        double dsq_acc = 0.0;
+        int bad = 0;
 
         // edges crossing internal tile boundaries, before any tile updates
-        for (int k = tid; k < (ntw - 1) * 2 * NG; k += BS) {
-            const int tt = 1 + k / (2 * NG), r = k % (2 * NG);
-            const int side = r / NG, q = r % NG;           // side 0: R-going, 1: L-going
-            const int lev = q / (G * nh), g = (q / nh) % G, mm = q % nh;
-            const int jb = (tile0 + tt) * CPT;             // first cell of tile tt
-            double v;
-            if (side == 0) v = L_psi[(size_t)(jb - 1 - c0) * n + (g * N + nh + mm) * 4 + 2 * lev + 1];
-            else v = L_psi[(size_t)(jb - c0) * n + (g * N + mm) * 4 + 2 * lev];
-            L_snap[(size_t)tt * 2 * NG + r] = v;
+        if (ntw > 1) {
+            for (int k = tid; k < (ntw - 1) * 2 * NG; k += BS) {
+                const int tt = 1 + k / (2 * NG), r = k % (2 * NG);
+                const int side = r / NG, q = r % NG;           // side 0: R-going, 1: L-going
+                const int lev = q / (G * nh), g = (q / nh) % G, mm = q % nh;
+                const int jb = (tile0 + tt) * CPT;             // first cell of tile tt
+                double v;
+                if (side == 0) v = L_psi[(size_t)(jb - 1 - c0) * n + (g * N + nh + mm) * 4 + 2 * lev + 1];
+                else v = L_psi[(size_t)(jb - c0) * n + (g * N + mm) * 4 + 2 * lev];
+                L_snap[(size_t)tt * 2 * NG + r] = v;
+            }
+            __syncthreads();
         }
-        __syncthreads();
 
         for (int tile = tile0; tile < tile1; ++tile) {
             const int tt = tile - tile0;
@@ -660,7 +688,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             const bool live = j < J;
             double *Lp = L_psi + (size_t)(j - c0) * n;          // this cell's iterate
             double *Lf = L_phi + (size_t)(j - c0) * 4 * G;
-            double xold[RPT];
+            double xold[RPT], bb[RPT];
             int expo = 0;
 
             // (1) b = constant part + lagged incident edge
@@ -686,7 +714,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                         else if (l == 0)
                             e = psi_g[(size_t)(j - 1) * n + i + 1];
                         else
-                            e = ld_agent(exq(l & 1, wg - 1, 1, lev, g, m - nh));
+                            e = take_edge(exq(l & 1, wg - 1, 1, lev, g, m - nh), &bad);
                         b += mu * e;
                     } else if (mu < 0.0 && (u & 1)) {
                         double e;
@@ -699,15 +727,18 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                         else if (l == 0)
                             e = psi_g[(size_t)(j + 1) * n + i - 1];
                         else
-                            e = ld_agent(exq(l & 1, wg + 1, 0, lev, g, m));
+                            e = take_edge(exq(l & 1, wg + 1, 0, lev, g, m), &bad);
                         b -= mu * e;
                     }
                 }
-                if constexpr (REF) s_wx[cl][i] = b;
-                else s_vec[cl][i] = b;
+                bb[r] = b;
+                if constexpr (!REF) s_vec[cl][i] = b;
             }
+            // the first partial of iteration l - 1 this thread sums is loaded
+            // now and checked after the solve
+            uint64_t pv0 = kPartEmpty;
+            if (tile == tile0 && l > 0 && tid < (int)nwg) pv0 = ld_bits(part_prev + tid);
             if constexpr (REF) {
-                __syncthreads();
                 // (2) FP64 residual r = b - A_j Psi^(l), matrix-free
                 double rr[RPT];
                 double mx = 0.0;
@@ -734,12 +765,12 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                             for (int gp = 0; gp < G; ++gp) sc += ss[gp] * Lf[gp * 4 + u];
                             sc *= 0.25 * S.dx[j];
                         }
-                        res = s_wx[cl][i] - lp + sc;
+                        res = bb[r] - lp + sc;
                     }
                     rr[r] = res;
                     mx = fmax(mx, fabs(res));
                 }
-                if constexpr (TPC <= 64) {
+                if constexpr (WAVE_CELL) {
 #pragma unroll
                     for (int off = TPC / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
                 } else {
@@ -754,7 +785,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) s_vec[cl][t + r * TPC] = (T)ldexp(rr[r], -expo);
             }
-            __syncthreads();
+            __syncthreads();   // s_vec complete; every read of this tile's Psi^(l) is done
 
             // (3) apply the inverse, one row per thread
             T acc[RPT];
@@ -780,10 +811,63 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                     }
                 }
             }
-            __syncthreads();   // every read of this tile's Psi^(l) is done
 
-            // (4) new iterate into LDS, scalar flux and its change
+            // (3b) stopping rule for iteration l - 1 (section 2.1): every
+            // workgroup sums the same tagged partials in the same order and
+            // takes the same decision
+            if (tile == tile0 && l > 0) {
+                double v = 0.0;
+                for (int k = tid; k < (int)nwg; k += BS) {
+                    uint64_t x = k == tid ? pv0 : ld_bits(part_prev + k);
+                    long spins = 0;
+#pragma clang loop unroll(disable)
+                    while (!part_ready(x, l - 1)) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (++spins > kSpinLimit) { bad = 1; break; }
+                        x = ld_bits(part_prev + k);
+                    }
+                    v += part_value(x);
+                }
+                if (bad) {
+                    __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    v = __builtin_nan("");
+                }
+                const double tot = block_sum_all<BS>(v, s_tmp);
+                const int iters = l;
+                const double e = sqrt(tot);
+                const double rho = iters >= 2 ? e / e_prev : __builtin_nan("");
+                int done = 0, status = OK;
+                if (!isfinite(e)) { done = 1; status = NONFINITE; }
+                else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
+                else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - e / e_prev))) done = 1;
+                else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
+                e_prev = e;
+                if (done) {
+                    // the final iterate Psi^(iters) and its flux leave LDS
+                    const int fin = (base + iters) & 1;
+                    double *pout = S.psi[fin] + (size_t)c0 * n;
+                    const int totp = (c1 - c0) * n;
+                    for (int k = tid; k < totp; k += BS) pout[k] = L_psi[k];
+                    double *fout = S.phi[fin] + (size_t)c0 * 4 * G;
+                    const int totf = (c1 - c0) * 4 * G;
+                    for (int k = tid; k < totf; k += BS) fout[k] = L_phi[k];
+                    if (wg == 0 && tid == 0) {
+                        Ctl *c = S.ctl;
+                        c->iter = iters;
+                        c->e_last = e;
+                        c->rho = rho;
+                        c->e_prev = e;
+                        c->status = status;
+                        c->done = 1;
+                    }
+                    return;
+                }
+            }
+
+            // (4) new iterate into LDS (the range's two end edges also go to
+            // the neighbours), scalar flux and its change
             double dsq = 0.0;
+            double xs[RPT];
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 const int i = t + r * TPC;
@@ -791,70 +875,60 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                 if (live && i < n) {
                     Lp[i] = x;
                     if (S.norm == 1) dsq += (x - xold[r]) * (x - xold[r]);
+                    const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
+                    if (j == c0 && wg > 0 && m < nh && !(u & 1))
+                        put_edge(exq(par, wg, 0, u >> 1, g, m), x);
+                    if (j == c1 - 1 && wg + 1 < (int)nwg && m >= nh && (u & 1))
+                        put_edge(exq(par, wg, 1, u >> 1, g, m - nh), x);
                 } else {
                     x = 0.0;
                 }
-                s_wx[cl][i] = (i < n ? s_w[(i >> 2) % N] : 0.0) * x;
+                xs[r] = x;
             }
-            __syncthreads();
-            if (live && t < 4 * G) {
-                const int g = t >> 2, u = t & 3;
-                double f = 0.0;
-                for (int m = 0; m < N; ++m) f += s_wx[cl][(g * N + m) * 4 + u];
-                const double f0 = Lf[t];
-                Lf[t] = f;
-                if (S.norm == 0) dsq += (f - f0) * (f - f0);
+            if (tree_phi) {
+                // phi_(g,u) = sum_m w_m psi_(g,m,u): the m index occupies lane
+                // bits 2 .. 1 + log2 N, summed by a butterfly within the wave
+                double wx = (t < n) ? s_w[(t >> 2) % N] * xs[0] : 0.0;
+                for (int off = 2 * N; off >= 4; off >>= 1) wx += __shfl_xor(wx, off, 64);
+                if (live && t < n && (t >> 2) % N == 0) {
+                    const int fi = (t / (4 * N)) * 4 + (t & 3);
+                    const double f0 = Lf[fi];
+                    Lf[fi] = wx;
+                    if (S.norm == 0) dsq += (wx - f0) * (wx - f0);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const int i = t + r * TPC;
+                    s_wx[cl][i] = (i < n ? s_w[(i >> 2) % N] : 0.0) * xs[r];
+                }
+                __syncthreads();
+                if (live && t < 4 * G) {
+                    const int g = t >> 2, u = t & 3;
+                    double f = 0.0;
+                    for (int m = 0; m < N; ++m) f += s_wx[cl][(g * N + m) * 4 + u];
+                    const double f0 = Lf[t];
+                    Lf[t] = f;
+                    if (S.norm == 0) dsq += (f - f0) * (f - f0);
+                }
             }
-            const double part = block_sum_t<BS>(dsq, s_tmp);
-            if (tid == 0) wg_sum += part;
+            dsq_acc += dsq;
+            if (tile + 1 < tile1) __syncthreads();   // s_vec / s_wx are reused by the next tile
         }
 
-        // (5) publish the two end edges of the range for iteration l + 1
+        // (5) the partial of iteration l, once this workgroup's stores (the
+        // published edges and the slots it emptied) have completed
         {
-            const int par = (l + 1) & 1;
-            for (int k = tid; k < 2 * NG; k += BS) {
-                const int side = k / NG, q = k % NG;
-                const int lev = q / (G * nh), g = (q / nh) % G, mm = q % nh;
-                if (side == 0 && wg > 0 && c1 > c0)
-                    st_agent(exq(par, wg, 0, lev, g, mm), L_psi[(g * N + mm) * 4 + 2 * lev]);
-                if (side == 1 && wg + 1 < (int)nwg && c1 > c0)
-                    st_agent(exq(par, wg, 1, lev, g, mm),
-                             L_psi[(size_t)(c1 - 1 - c0) * n + (g * N + nh + mm) * 4 + 2 * lev + 1]);
-            }
+            const double v = wave_sum(dsq_acc);
+            if ((tid & 63) == 0) s_part[tid >> 6] = v;
         }
-
-        // (6) barrier + reduction; every workgroup decides identically
-        double tot = 0.0;
-        const bool ok = grid_sync_local<BS>(S, nwg, l, wg_sum, s_flag, s_tmp, &tot);
-        const int iters = l + 1;
-        const double e = sqrt(tot);
-        const double rho = iters >= 2 ? e / e_prev : __builtin_nan("");
-        int done = 0, status = OK;
-        if (!ok) done = 1;
-        else if (!isfinite(e)) { done = 1; status = NONFINITE; }
-        else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
-        else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - e / e_prev))) done = 1;
-        else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
-        e_prev = e;
-        if (done) {
-            // the final iterate and its flux leave LDS
-            const int fin = (base + iters) & 1;
-            double *pout = S.psi[fin] + (size_t)c0 * n;
-            const int totp = (c1 - c0) * n;
-            for (int k = tid; k < totp; k += BS) pout[k] = L_psi[k];
-            double *fout = S.phi[fin] + (size_t)c0 * 4 * G;
-            const int totf = (c1 - c0) * 4 * G;
-            for (int k = tid; k < totf; k += BS) fout[k] = L_phi[k];
-            if (wg == 0 && tid == 0) {
-                Ctl *c = S.ctl;
-                c->iter = iters;
-                c->e_last = e;
-                c->rho = rho;
-                c->e_prev = e;
-                c->status = status;
-                c->done = 1;
-            }
-            break;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < BS / 64; ++w) s += s_part[w];
+            st_bits(part_bits + (size_t)(l & 1) * nwg + wg, part_encode(s, l));
         }
     }
 }
@@ -1180,6 +1254,7 @@ static hipError_t dispatch(bool fp32, int np, bool res, int bs, F f) {
 
 template <typename T, int NP, bool RES, int BS>
 static hipError_t launch_local_t(const Slab &S, const StepIO &io, int nwg, int ntiles, size_t dyn, hipStream_t st) {
+    if (RES && nwg != ntiles) return hipErrorInvalidValue;
     const void *f = (const void *)&k_oci_local<T, NP, RES, BS>;
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
@@ -1255,7 +1330,7 @@ hipError_t launch_oci_local(const Slab &S, const StepIO &io, bool fp32, int np, 
     return dispatch(fp32, np, res, bs, LaunchLocalF{S, io, nwg, ntiles, dyn, st});
 }
 
-hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, hipStream_t st) {
+hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, hipStream_t st, int local_nwg) {
     hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, st, S);
     {
         const size_t tot = (size_t)S.J * S.n;
@@ -1265,8 +1340,10 @@ hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, h
         const size_t tot = (size_t)S.J * S.G * S.N * 4;
         hipLaunchKernelGGL(k_broadcast_state, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S);
     }
-    const size_t tot = (size_t)S.J * S.G * 4;
-    hipLaunchKernelGGL(k_phi0, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S);
+    size_t tot = (size_t)S.J * S.G * 4;
+    const size_t nex = (size_t)4 * local_nwg * S.N * S.G;
+    if (nex > tot) tot = nex;
+    hipLaunchKernelGGL(k_phi0, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S, local_nwg);
     return hipGetLastError();
 }
 

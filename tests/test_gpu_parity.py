@@ -212,11 +212,13 @@ def test_state_roundtrip_restart():
 
 
 @pytest.mark.parametrize("mode", [{"OCI_MODE": "global"}, {"OCI_NO_RESIDENT": "1"},
-                                  {"OCI_BLOCK": "256"}, {"OCI_BAR_GROUP": "3"}])
+                                  {"OCI_BLOCK": "256"}, {"OCI_BAR_GROUP": "3"}, {"OCI_MAX_WG": "3"},
+                                  {"OCI_MAX_WG": "3", "OCI_MODE": "global"}])
 @pytest.mark.parametrize("name", ["regions512_n64", "multigroup128_n256", "odd_N6_n24"])
 def test_kernel_variants_lockstep(name, mode, monkeypatch):
     """Every launch variant (global-memory kernel, streamed factors, block size,
-    barrier arrival groups) gives the oracle's lock-step answer."""
+    barrier arrival groups, several tiles per workgroup) gives the oracle's
+    lock-step answer."""
     for k, v in mode.items():
         monkeypatch.setenv(k, v)
     p, steps = CASES[name]
