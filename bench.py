@@ -164,9 +164,14 @@ def roofline_for(prim, probs, fp32):
     achieved = bpc * cpl / avg_launch_s / 1e9
     label = kernel_label(prim["configs"][0], fp32, np_)
     tr = recorded_traffic(label)
+    resident = bool(prim["configs"][0].get("resident"))
+    note = ("inverse rows held in registers for the whole step: the algorithmic bytes count the "
+            "factor stream of every iteration, which this kernel does not re-read, so frac can "
+            "exceed 1; traffic is the HBM bytes actually moved" if resident else
+            "inverse rows streamed from memory every iteration")
     return dict(bound="hbm", achieved=round(achieved, 1), peak=MI355X_HBM_GBS, unit="GB/s",
                 frac=round(achieved / MI355X_HBM_GBS, 4),
-                traffic=None if tr is None else round(tr * cpl, 1),
+                traffic=None if tr is None else round(tr * cpl, 1), note=note,
                 kernel=label, avg_launch_us=round(avg_launch_s * 1e6, 2),
                 cell_iterations_per_launch=round(cpl, 1), bytes_per_cell_iteration=bpc,
                 flops_per_cell_iteration=2 * n * n,

@@ -16,14 +16,13 @@ constexpr int kBlock = 256;
 // kBarGroup before one leader per group arrives at the top counter.
 constexpr int kBarStride = 32;
 constexpr int kBarGroup = 16;
-// Hand-off slots of the workgroup-local kernel.  An exchange slot holding
-// kEdgeEmpty has been consumed (a NaN payload no arithmetic produces; a value
-// with this bit pattern is replaced by the default NaN before it is
-// published).  A partial-sum slot holds the bits of a non-negative double
-// whose low kPartTagBits mantissa bits carry the iteration number modulo
-// 2^kPartTagBits; kPartEmpty (sign bit set) never matches a tag.
-constexpr uint64_t kEdgeEmpty = 0xFFF4C0DE5E4714E1ull;
-constexpr uint64_t kPartEmpty = ~0ull;
+// Hand-off slots of the workgroup-local kernel.  An edge value travels as two
+// 64-bit words, each holding one 32-bit half of the double below a 32-bit tag
+// (the iteration that will read it); a slot reset to kSlotEmpty carries no
+// valid tag.  A partial-sum slot holds the bits of a non-negative double whose
+// low kPartTagBits mantissa bits carry the iteration number modulo
+// 2^kPartTagBits; kSlotEmpty (sign bit set) never matches a tag either.
+constexpr uint64_t kSlotEmpty = ~0ull;
 constexpr int kPartTagBits = 4;
 
 // Control block of one slab problem, in the workspace.  Written by the step
@@ -62,13 +61,13 @@ struct Slab {
     double *phi[2];              // [J][G][4]   scalar flux of each iterate
     double *psi_prev;            // [J][G][N][2] state psi_{k-1/2}
     double *crhs;                // [J][G][N][4] constant part of b for the current step
-    double *exch;                // [2][max workgroups][2][2][G][N/2] boundary edges between workgroups
+    double *exch;                // [2][max workgroups][2][2][G][N/2][2 words] boundary edges between workgroups
     double *si_linv;             // [J][G][N][16] inverse of the 4x4 SI cell matrix
     double *si_resp;             // [J][G][N][8] response of the cell to its two incident edges
     double *si_msw;              // [J][NG][4] 2x2 edge-to-edge map, in sweep order
     double *si_alpha;            // [J][NG][2] outgoing edges of the uncoupled solution, sweep order
     double *si_ein;              // [J][NG][2] incident edges met by the sweep, sweep order
-    double *partials;            // [2][max workgroups] per-workgroup sums (iteration parity)
+    double *partials;            // [4][max workgroups] per-workgroup sums (by iteration mod 2, or mod 4)
     Ctl *ctl;
     // grid barrier words, 256 bytes apart: [0] arrivals of group leaders,
     // [kBarStride] release flag, [(2 + k) * kBarStride] arrivals in group k

@@ -109,9 +109,9 @@ __device__ inline void phi0_elem(const Slab &S, size_t t) {
 __global__ __launch_bounds__(kBlock) void k_phi0(Slab S, int nwg) {
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < (size_t)S.J * S.G * 4) phi0_elem(S, t);
-    const size_t nex = (size_t)4 * nwg * S.N * S.G;
-    if (t < nex) reinterpret_cast<uint64_t *>(S.exch)[t] = kEdgeEmpty;
-    if (t < (size_t)2 * nwg) reinterpret_cast<uint64_t *>(S.partials)[t] = kPartEmpty;
+    const size_t nex = (size_t)8 * nwg * S.N * S.G;
+    if (t < nex) reinterpret_cast<uint64_t *>(S.exch)[t] = kSlotEmpty;
+    if (t < (size_t)4 * nwg) reinterpret_cast<uint64_t *>(S.partials)[t] = kSlotEmpty;
 }
 
 // psi of the first iterate from the state (both time levels).
@@ -505,26 +505,31 @@ __device__ inline void st_bits(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Edge hand-off between neighbouring workgroups: the producer stores the
-// value into an empty slot; the consumer waits until the slot is no longer
-// empty, takes the value and marks the slot empty again.  The wait is
-// bounded: on expiry *bad is raised and the value is NaN.
-__device__ inline void put_edge(uint64_t *slot, double v) {
-    uint64_t b = (uint64_t)__double_as_longlong(v);
-    if (b == kEdgeEmpty) b = 0x7FF8000000000000ull;
-    st_bits(slot, b);
+// Edge hand-off between neighbouring workgroups: the producer stores each
+// 32-bit half of the value beside the tag of the iteration that will read it,
+// as two single-copy-atomic 64-bit words; the consumer waits until both words
+// carry its own iteration.  The slots are double-buffered by iteration parity,
+// so a stale word carries the tag of two iterations earlier; no slot is ever
+// reset inside a launch.  The wait is bounded: on expiry *bad is raised and
+// the value is NaN.
+__device__ inline void put_edge(uint64_t *slot, double v, int tag) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t t = (uint64_t)(uint32_t)tag << 32;
+    st_bits(slot, t | (b & 0xFFFFFFFFull));
+    st_bits(slot + 1, t | (b >> 32));
 }
-__device__ inline double take_edge(uint64_t *slot, int *bad) {
-    uint64_t b = ld_bits(slot);
+__device__ inline double take_edge(const uint64_t *slot, int tag, int *bad) {
+    const uint32_t want = (uint32_t)tag;
+    uint64_t lo = ld_bits(slot), hi = ld_bits(slot + 1);
     long spins = 0;
 #pragma clang loop unroll(disable)
-    while (b == kEdgeEmpty) {
+    while ((uint32_t)(lo >> 32) != want || (uint32_t)(hi >> 32) != want) {
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) { *bad = 1; break; }
-        b = ld_bits(slot);
+        if (++spins > kSpinLimit) { *bad = 1; return __builtin_nan(""); }
+        lo = ld_bits(slot);
+        hi = ld_bits(slot + 1);
     }
-    st_bits(slot, kEdgeEmpty);
-    return __longlong_as_double((long long)b);
+    return __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
 }
 
 // Partial sums carry the iteration that produced them in their lowest
@@ -541,33 +546,83 @@ __device__ inline bool part_ready(uint64_t b, int l) {
 }
 __device__ inline double part_value(uint64_t b) { return __longlong_as_double((long long)(b & ~kTagMask)); }
 
-// Sum over the workgroup in a fixed order, returned to every thread.
-template <int BS>
-__device__ inline double block_sum_all(double v, double *s_tmp) {
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) s_tmp[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < BS / 64; ++w) t += s_tmp[w];
-    return t;
+// Cross-lane moves inside a row of 16 lanes (DPP: no LDS round trip), for the
+// wave-level reductions of the workgroup-local kernel.  Called with every lane
+// of the wave active.
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <- 7 - i within 8
+constexpr int kDppMirror = 0x140;      // lane i <- 15 - i within 16
+constexpr int kDppRor4 = 0x124;        // rotate the row by 4 lanes
+constexpr int kDppRor8 = 0x128;        // rotate the row by 8 lanes
+template <int CTRL>
+__device__ inline int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const int lo = dpp_i32<CTRL>(__double2loint(v));
+    const int hi = dpp_i32<CTRL>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double readlane_f64(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+// Sum over the 64 lanes of the wave in a fixed order; every lane gets the
+// same value (each butterfly step adds two equal-order partial sums, and
+// floating-point addition is commutative).
+__device__ inline double wave_sum_dpp(double v) {
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppHalfMirror>(v);
+    v += dpp_f64<kDppMirror>(v);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+// Maximum over aligned groups of TPC lanes (TPC = 8 .. 64).
+template <int TPC>
+__device__ inline int seg_max_i32(int v) {
+    v = max(v, dpp_i32<kDppXor1>(v));
+    v = max(v, dpp_i32<kDppXor2>(v));
+    v = max(v, dpp_i32<kDppHalfMirror>(v));
+    if constexpr (TPC >= 16) v = max(v, dpp_i32<kDppMirror>(v));
+    if constexpr (TPC == 32) v = max(v, __shfl_xor(v, 16, 64));
+    if constexpr (TPC == 64)
+        v = max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+                max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+    return v;
+}
+
+// Orders the LDS accesses of one wave before and after it (the wave's LDS
+// operations complete in issue order; this only keeps the compiler from
+// moving them across).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Workgroup-local persistent OCI kernel.  Each workgroup owns the contiguous
 // cells [c0, c1) for the whole step and keeps their iterate Psi and scalar
 // flux phi in LDS (dynamic shared memory: [cells][n] Psi, [cells][4G] phi,
 // then per internal tile boundary a snapshot of the 2NG edge values that
-// cross it).  Only the edges at the two ends of the range cross workgroups,
-// handed to the neighbour through single-use slots (put_edge / take_edge);
-// iterate 0's neighbour edges come from global memory (written by earlier
-// launches).  There is no grid barrier: a workgroup waits only for its two
-// neighbours' edges, and for the tagged partial sums of the previous
-// iteration, which it needs for the stopping decision.  The slots of an
-// iteration's partials are reused two iterations later, and a workgroup can
-// only get there after every workgroup has published the partial of the
-// iteration in between, which it does after its reads (and after the slots
-// it emptied are stored), so no slot is overwritten while still needed.  At
-// the end the final Psi and phi are written to global memory.
+// cross it; with register-resident rows, one tile per workgroup and Psi and
+// phi three times, [3][cells][n] and [3][cells][4G]).  Only the edges at the
+// two ends of the range cross
+// workgroups, handed to the neighbour through tagged slots (put_edge /
+// take_edge); iterate 0's neighbour edges come from global memory (written by
+// earlier launches).  There is no grid barrier: a workgroup waits only for its
+// two neighbours' edges, and for the tagged partial sums it needs for the
+// stopping decision.  An edge slot is written again two iterations later,
+// and the writer cannot get there before the reader has taken the old value:
+// the writer's next iteration needs the reader's edges, which the reader only
+// publishes after that read.  A partial-sum slot (four of them, by iteration
+// mod 4) is written again four iterations later, after its writer has taken
+// a decision that needs every workgroup's partial of an iteration whose end
+// follows that workgroup's last read of the slot.  No store has to complete
+// before another is issued.  At the end the final Psi and phi are written to
+// global memory.
 // Template parameters as k_oci_step.
 template <typename T, int NP, bool RES, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
@@ -579,6 +634,20 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     constexpr int V = 16 / sizeof(T);
     constexpr int NV = NP / V;
     constexpr bool CACHE = RES && REF;
+    // Register-resident rows: one tile per workgroup (launched with nwg =
+    // ntiles), a cell's rows in one wave, and three LDS copies of Psi and phi
+    // (the iterate, the one being formed, and the one before).  Each wave
+    // then runs its cell's iteration on its own, with one workgroup barrier
+    // per iteration; the stopping decision lags one more iteration (its
+    // partial sums have long arrived when it is taken) and takes effect at
+    // that barrier.
+    constexpr bool DB = RES;
+    static_assert(!DB || TPC <= 64, "resident rows: one cell per wave or less");
+    static_assert(BS <= 1024, "wave sums are added within one row of 16 lanes");
+    constexpr int NCOPY = DB ? 3 : 1;   // LDS copies of Psi and phi
+    constexpr int LAG = DB ? 2 : 1;     // iteration l decides on e_(l - LAG + 1)
+    constexpr int PV = 4;               // partial sums per lane loaded ahead of the decision
+    constexpr bool WAVE_CELL = TPC <= 64;   // a cell's rows lie in one wave (then RPT = 1)
     typedef typename Vec16<T>::type VT;
 
     extern __shared__ __align__(16) double s_dyn[];
@@ -590,30 +659,32 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     __shared__ double s_mu[NP / 4], s_w[NP / 4];
     __shared__ double s_tmp[BS / 64 + 1];
     __shared__ double s_max[BS / 64];
-    __shared__ double s_part[BS / 64];
+    __shared__ double s_part[2][BS / 64];   // per-wave partial sums, by iteration parity
+    __shared__ double s_dec[2][4];          // decision (done, status, e, rho), by iteration parity
+    __shared__ double s_psum[2][BS / 64];   // per-wave sums of the tagged partials, by iteration parity
+    __shared__ double s_eprev[2];           // e of the last decision, by iteration parity (kept out of registers)
 
     const int tid = threadIdx.x;
-    const int cl = tid / TPC;
-    const int t = tid % TPC;
+    const int dec_wave = (BS / 64) / 2;   // the wave that takes the stopping decision
     const int J = S.J, N = S.N, G = S.G, n = S.n, nh = S.N / 2, NG = S.N * S.G;
     const unsigned nwg = gridDim.x;
     const int wg = blockIdx.x;
-    // register-resident rows: one tile per workgroup (launched with nwg = ntiles)
     const int tile0 = RES ? wg : (int)(((long)ntiles * wg) / nwg);
     const int tile1 = RES ? wg + 1 : (int)(((long)ntiles * (wg + 1)) / nwg);
     const int ntw = tile1 - tile0;
     const int c0 = tile0 * CPT;
     const int c1 = min(tile1 * CPT, J);
     const int ncell = ntw * CPT;
-    double *L_psi = s_dyn;                                   // [ncell][n]
-    double *L_phi = L_psi + (size_t)ncell * n;               // [ncell][4G]
-    double *L_snap = L_phi + (size_t)ncell * 4 * G;          // [ntw][2][NG]: R-going, L-going
-    // exchange buffer [2 parity][nwg][2 side][2 lev][G][nh]; side 0: my first
-    // cell's L corners of mu<0 angles, side 1: my last cell's R corners of mu>0
-    const size_t exw = (size_t)2 * 2 * G * nh;
+    double *L_psi0 = s_dyn;                                        // [NCOPY][ncell][n]
+    double *L_phi0 = L_psi0 + (size_t)NCOPY * ncell * n;           // [NCOPY][ncell][4G]
+    double *L_snap = L_phi0 + (size_t)NCOPY * ncell * 4 * G;       // [ntw][2][NG]: R-going, L-going
+    // exchange buffer [2 parity][nwg][2 side][2 lev][G][nh] slots of two
+    // words; side 0: my first cell's L corners of mu<0 angles, side 1: my
+    // last cell's R corners of mu>0
+    const size_t exw = (size_t)2 * 2 * G * nh;   // edge slots per (parity, workgroup)
     uint64_t *exch_bits = reinterpret_cast<uint64_t *>(S.exch);
     auto exq = [&](int par, int w, int side, int lev, int g, int mm) -> uint64_t * {
-        return exch_bits + (((size_t)par * nwg + w) * 2 + side) * (exw / 2) + ((size_t)lev * G + g) * nh + mm;
+        return exch_bits + 2 * ((((size_t)par * nwg + w) * 2 + side) * (exw / 2) + ((size_t)lev * G + g) * nh + mm);
     };
 
     for (int m = tid; m < N; m += BS) { s_mu[m] = S.mu[m]; s_w[m] = S.w[m]; }
@@ -621,11 +692,12 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     const T *Xall = reinterpret_cast<const T *>(S.X);
     VT xr[RES ? NV : 1];
     if constexpr (RES) {
-        const int j = tile0 * CPT + cl;
-        if (ntw > 0 && j < J) {
+        const int j = tile0 * CPT + tid / TPC;
+        if (j < J) {
             const T *Xc = Xall + (size_t)j * NP * NP;
 #pragma unroll
-            for (int kv = 0; kv < NV; ++kv) xr[kv] = *reinterpret_cast<const VT *>(Xc + ((size_t)kv * NP + t) * V);
+            for (int kv = 0; kv < NV; ++kv)
+                xr[kv] = *reinterpret_cast<const VT *>(Xc + ((size_t)kv * NP + tid % TPC) * V);
         }
     }
     // the iterate and its scalar flux into LDS
@@ -633,43 +705,147 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     {
         const double *pin = S.psi[base] + (size_t)c0 * n;
         const int tot = (c1 - c0) * n;
-        for (int k = tid; k < tot; k += BS) L_psi[k] = pin[k];
+        for (int k = tid; k < tot; k += BS) L_psi0[k] = pin[k];
         const double *fin = S.phi[base] + (size_t)c0 * 4 * G;
         const int totf = (c1 - c0) * 4 * G;
-        for (int k = tid; k < totf; k += BS) L_phi[k] = fin[k];
+        for (int k = tid; k < totf; k += BS) L_phi0[k] = fin[k];
     }
     __syncthreads();
     if constexpr (CACHE) {
+        const int cl = tid / TPC, i = tid % TPC;
         const int j = tile0 * CPT + cl;
-        const int i = t;
-        if (ntw > 0 && j < J && i < n) {
+        if (j < J && i < n) {
             const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
             lc_row(S, j, g, s_mu[m], u, s_coef[cl][i]);
             s_crow[cl][i] = S.crhs[(size_t)j * n + i];
         }
-        if (ntw > 0 && j < J && t < G * G) s_scat[cl][t] = 0.25 * S.dx[j] * S.sigma_s[(size_t)j * G * G + t];
+        if (j < J && i < G * G) s_scat[cl][i] = 0.25 * S.dx[j] * S.sigma_s[(size_t)j * G * G + i];
         __syncthreads();
     }
 
-    // Iteration l forms Psi^(l+1).  Its first tile computes the new values
-    // (steps 1-3) before the decision on iteration l - 1 is known; the
-    // decision is taken before anything in LDS is overwritten, so on a stop
-    // LDS still holds the final iterate.
-    constexpr bool WAVE_CELL = TPC <= 64;   // a cell's rows lie in one wave
     const bool tree_phi = WAVE_CELL && (N & (N - 1)) == 0;
     uint64_t *part_bits = reinterpret_cast<uint64_t *>(S.partials);
+    const double *__restrict__ psi_g = S.psi[base];   // the iterate in global memory: only read at l = 0
     double e_prev = __builtin_nan("");
+    uint64_t pv[PV];   // the decision wave's partial sums, loaded at the end of the previous iteration
+#pragma unroll
+    for (int r = 0; r < PV; ++r) pv[r] = kSlotEmpty;
+    // Iteration l forms Psi^(l+1).  With one copy of Psi, one wave decides at
+    // its start, while the others wait for the neighbours' edges, on e_l (the
+    // partials of iteration l - 1); the outcome reaches every wave through
+    // the barrier that precedes the solve, before anything in LDS is
+    // overwritten.  With three copies the decision is on e_(l-1): every wave
+    // loads its share of the partials of iteration l - 2 at the start, sums
+    // it at the end, and after the barrier that ends the iteration every
+    // thread adds the shares in the same order and applies the rule.  Either
+    // way LDS still holds the final iterate when the decision stops the step.
     for (int l = 0;; ++l) {
-        const int cur = (base + l) & 1;
-        const double *__restrict__ psi_g = S.psi[cur];   // global iterate: only read at l = 0
-        const uint64_t *part_prev = part_bits + (size_t)((l + 1) & 1) * nwg;   // partials of iteration l - 1
+        // lane indices are re-derived every iteration from an opaque copy, so
+        // the compiler does not keep per-lane addresses live across the loop
+        // (registers are scarce next to the resident inverse rows)
+        int tid_o = tid;
+        asm volatile("" : "+v"(tid_o));
+        const int cl = tid_o / TPC;
+        const int t = tid_o % TPC;
+        const int cb = l % NCOPY;                        // LDS copy holding Psi^(l)
+        const int nb = (l + 1) % NCOPY;                  // ... Psi^(l+1)
+        double *L_psi = L_psi0 + (size_t)cb * ncell * n;
+        double *L_phi = L_phi0 + (size_t)cb * ncell * 4 * G;
+        double *N_psi = L_psi0 + (size_t)nb * ncell * n;
+        double *N_phi = L_phi0 + (size_t)nb * ncell * 4 * G;
+        const int lp = l - LAG;                          // iteration whose partials are decided on
+        const uint64_t *part_prev = part_bits + (size_t)(lp & 3) * nwg;
         const int par = (l + 1) & 1;                     // exchange parity this iteration publishes
+        const bool dec = !DB && (tid_o >> 6) == dec_wave && lp >= 0;   // this wave decides (wave-uniform)
         double dsq_acc = 0.0;
         int bad = 0;
+        // three copies: this wave's share of the partials of iteration lp,
+        // slots [w Sw, (w + 1) Sw), one per lane (more past 64 lanes)
+        constexpr int W = BS / 64;
+        const int Sw = ((int)nwg + W - 1) / W;
+        auto qslot = [&](int tq, bool *on) -> int {   // (re-derived where needed, to spare registers)
+            const int q = (tq >> 6) * Sw + (tq & 63);
+            *on = DB && lp >= 0 && (tq & 63) < Sw && q < (int)nwg;
+            return q;
+        };
+        uint64_t qv = kSlotEmpty;
+        {
+            bool on;
+            const int q = qslot(tid_o, &on);
+            if (on) qv = ld_bits(part_prev + q);
+        }
+
+        // Stopping rule (section 2.1) on e_(lp+1), the change made by
+        // iteration lp, in the decision wave: every workgroup's decision wave
+        // sums the same tagged partials in the same order (lane k holds k,
+        // k + 64, ...) and takes the same decision, left in s_dec.
+        auto wait_part = [&](uint64_t x, int k) -> double {
+            long spins = 0;
+#pragma clang loop unroll(disable)
+            while (!part_ready(x, lp)) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kSpinLimit) { bad = 1; break; }
+                x = ld_bits(part_prev + k);
+            }
+            return part_value(x);
+        };
+        auto decide_wave = [&]() {
+            const int lane = tid_o & 63;
+            double v = 0.0;
+#pragma unroll
+            for (int r = 0; r < PV; ++r)
+                if (lane + 64 * r < (int)nwg) v += wait_part(pv[r], lane + 64 * r);
+            for (int k = lane + 64 * PV; k < (int)nwg; k += 64) v += wait_part(ld_bits(part_prev + k), k);
+            if (bad) {
+                __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                v = __builtin_nan("");
+            }
+            const double tot = wave_sum_dpp(v);
+            const int iters = lp + 1;
+            const double e = sqrt(tot);
+            const double rho = iters >= 2 ? e / e_prev : __builtin_nan("");
+            int done = 0, status = OK;
+            if (!isfinite(e)) { done = 1; status = NONFINITE; }
+            else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
+            else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - rho))) done = 1;
+            else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
+            e_prev = e;
+            if (lane == 0) {
+                s_dec[l & 1][0] = done;
+                s_dec[l & 1][1] = status;
+                s_dec[l & 1][2] = e;
+                s_dec[l & 1][3] = rho;
+            }
+        };
+        // After a stop: the final iterate Psi^(lp+1) and its flux leave LDS.
+        auto finish = [&](double e, double rho, int status) {
+            const int iters = lp + 1;
+            const int fin = (base + iters) & 1;
+            const int db = iters % NCOPY;
+            const double *D_psi = L_psi0 + (size_t)db * ncell * n;
+            const double *D_phi = L_phi0 + (size_t)db * ncell * 4 * G;
+            double *pout = S.psi[fin] + (size_t)c0 * n;
+            const int totp = (c1 - c0) * n;
+            for (int k = tid_o; k < totp; k += BS) pout[k] = D_psi[k];
+            double *fout = S.phi[fin] + (size_t)c0 * 4 * G;
+            const int totf = (c1 - c0) * 4 * G;
+            for (int k = tid_o; k < totf; k += BS) fout[k] = D_phi[k];
+            if (wg == 0 && tid_o == 0) {
+                Ctl *c = S.ctl;
+                c->iter = iters;
+                c->e_last = e;
+                c->rho = rho;
+                c->e_prev = e;
+                c->status = status;
+                c->done = 1;
+            }
+        };
+
+        if (dec) decide_wave();
 
         // edges crossing internal tile boundaries, before any tile updates
-        if (ntw > 1) {
-            for (int k = tid; k < (ntw - 1) * 2 * NG; k += BS) {
+        if (!DB && ntw > 1) {
+            for (int k = tid_o; k < (ntw - 1) * 2 * NG; k += BS) {
                 const int tt = 1 + k / (2 * NG), r = k % (2 * NG);
                 const int side = r / NG, q = r % NG;           // side 0: R-going, 1: L-going
                 const int lev = q / (G * nh), g = (q / nh) % G, mm = q % nh;
@@ -686,11 +862,12 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             const int tt = tile - tile0;
             const int j = tile * CPT + cl;
             const bool live = j < J;
-            double *Lp = L_psi + (size_t)(j - c0) * n;          // this cell's iterate
-            double *Lf = L_phi + (size_t)(j - c0) * 4 * G;
+            const double *Lp = L_psi + (size_t)(j - c0) * n;    // this cell's iterate
+            const double *Lf = L_phi + (size_t)(j - c0) * 4 * G;
+            double *Np = N_psi + (size_t)(j - c0) * n;          // ... and where the next one goes
+            double *Nf = N_phi + (size_t)(j - c0) * 4 * G;
             double xold[RPT], bb[RPT];
             int expo = 0;
-
             // (1) b = constant part + lagged incident edge
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -714,7 +891,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                         else if (l == 0)
                             e = psi_g[(size_t)(j - 1) * n + i + 1];
                         else
-                            e = take_edge(exq(l & 1, wg - 1, 1, lev, g, m - nh), &bad);
+                            e = take_edge(exq(l & 1, wg - 1, 1, lev, g, m - nh), l, &bad);
                         b += mu * e;
                     } else if (mu < 0.0 && (u & 1)) {
                         double e;
@@ -727,21 +904,18 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                         else if (l == 0)
                             e = psi_g[(size_t)(j + 1) * n + i - 1];
                         else
-                            e = take_edge(exq(l & 1, wg + 1, 0, lev, g, m), &bad);
+                            e = take_edge(exq(l & 1, wg + 1, 0, lev, g, m), l, &bad);
                         b -= mu * e;
                     }
                 }
                 bb[r] = b;
                 if constexpr (!REF) s_vec[cl][i] = b;
             }
-            // the first partial of iteration l - 1 this thread sums is loaded
-            // now and checked after the solve
-            uint64_t pv0 = kPartEmpty;
-            if (tile == tile0 && l > 0 && tid < (int)nwg) pv0 = ld_bits(part_prev + tid);
+            if (bad) __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if constexpr (REF) {
-                // (2) FP64 residual r = b - A_j Psi^(l), matrix-free
+                // (2) FP64 residual r = b - A_j Psi^(l), matrix-free, scaled
+                // by the power of two of its largest entry in the cell
                 double rr[RPT];
-                double mx = 0.0;
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
                     const int i = t + r * TPC;
@@ -768,24 +942,36 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                         res = bb[r] - lp + sc;
                     }
                     rr[r] = res;
-                    mx = fmax(mx, fabs(res));
                 }
                 if constexpr (WAVE_CELL) {
-#pragma unroll
-                    for (int off = TPC / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+                    // biased exponent of the largest |r| (0x7FF: not finite)
+                    int ex = (int)(((uint64_t)__double_as_longlong(rr[0]) >> 52) & 0x7FF);
+                    ex = seg_max_i32<TPC>(ex);
+                    if (ex > 0 && ex < 0x7FF) expo = ex - 1022;
                 } else {
+                    double mx = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) mx = fmax(mx, fabs(rr[r]));
 #pragma unroll
                     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-                    if ((tid & 63) == 0) s_max[tid >> 6] = mx;
+                    if ((tid_o & 63) == 0) s_max[tid_o >> 6] = mx;
                     __syncthreads();
                     mx = 0.0;
                     for (int w = cl * (TPC / 64); w < (cl + 1) * (TPC / 64); ++w) mx = fmax(mx, s_max[w]);
+                    if (mx > 0.0 && isfinite(mx)) frexp(mx, &expo);
                 }
-                if (mx > 0.0 && isfinite(mx)) frexp(mx, &expo);
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) s_vec[cl][t + r * TPC] = (T)ldexp(rr[r], -expo);
             }
-            __syncthreads();   // s_vec complete; every read of this tile's Psi^(l) is done
+            if constexpr (DB) {
+                wave_sync();   // the cell's s_vec is complete (the cell is this wave's)
+            } else {
+                __syncthreads();   // s_vec and the decision complete; every read of this tile's Psi^(l) is done
+                if (tile == tile0 && lp >= 0 && s_dec[l & 1][0] != 0.0) {
+                    finish(s_dec[l & 1][2], s_dec[l & 1][3], (int)s_dec[l & 1][1]);
+                    return;
+                }
+            }
 
             // (3) apply the inverse, one row per thread
             T acc[RPT];
@@ -812,60 +998,8 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                 }
             }
 
-            // (3b) stopping rule for iteration l - 1 (section 2.1): every
-            // workgroup sums the same tagged partials in the same order and
-            // takes the same decision
-            if (tile == tile0 && l > 0) {
-                double v = 0.0;
-                for (int k = tid; k < (int)nwg; k += BS) {
-                    uint64_t x = k == tid ? pv0 : ld_bits(part_prev + k);
-                    long spins = 0;
-#pragma clang loop unroll(disable)
-                    while (!part_ready(x, l - 1)) {
-                        __builtin_amdgcn_s_sleep(1);
-                        if (++spins > kSpinLimit) { bad = 1; break; }
-                        x = ld_bits(part_prev + k);
-                    }
-                    v += part_value(x);
-                }
-                if (bad) {
-                    __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    v = __builtin_nan("");
-                }
-                const double tot = block_sum_all<BS>(v, s_tmp);
-                const int iters = l;
-                const double e = sqrt(tot);
-                const double rho = iters >= 2 ? e / e_prev : __builtin_nan("");
-                int done = 0, status = OK;
-                if (!isfinite(e)) { done = 1; status = NONFINITE; }
-                else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
-                else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - e / e_prev))) done = 1;
-                else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
-                e_prev = e;
-                if (done) {
-                    // the final iterate Psi^(iters) and its flux leave LDS
-                    const int fin = (base + iters) & 1;
-                    double *pout = S.psi[fin] + (size_t)c0 * n;
-                    const int totp = (c1 - c0) * n;
-                    for (int k = tid; k < totp; k += BS) pout[k] = L_psi[k];
-                    double *fout = S.phi[fin] + (size_t)c0 * 4 * G;
-                    const int totf = (c1 - c0) * 4 * G;
-                    for (int k = tid; k < totf; k += BS) fout[k] = L_phi[k];
-                    if (wg == 0 && tid == 0) {
-                        Ctl *c = S.ctl;
-                        c->iter = iters;
-                        c->e_last = e;
-                        c->rho = rho;
-                        c->e_prev = e;
-                        c->status = status;
-                        c->done = 1;
-                    }
-                    return;
-                }
-            }
-
-            // (4) new iterate into LDS (the range's two end edges also go to
-            // the neighbours), scalar flux and its change
+            // (4) new iterate (the range's two end edges also go to the
+            // neighbours), scalar flux and its change
             double dsq = 0.0;
             double xs[RPT];
 #pragma unroll
@@ -873,13 +1007,13 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                 const int i = t + r * TPC;
                 double x = REF ? xold[r] + ldexp((double)acc[r], expo) : (double)acc[r];
                 if (live && i < n) {
-                    Lp[i] = x;
+                    Np[i] = x;
                     if (S.norm == 1) dsq += (x - xold[r]) * (x - xold[r]);
                     const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
                     if (j == c0 && wg > 0 && m < nh && !(u & 1))
-                        put_edge(exq(par, wg, 0, u >> 1, g, m), x);
+                        put_edge(exq(par, wg, 0, u >> 1, g, m), x, l + 1);
                     if (j == c1 - 1 && wg + 1 < (int)nwg && m >= nh && (u & 1))
-                        put_edge(exq(par, wg, 1, u >> 1, g, m - nh), x);
+                        put_edge(exq(par, wg, 1, u >> 1, g, m - nh), x, l + 1);
                 } else {
                     x = 0.0;
                 }
@@ -887,13 +1021,20 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             }
             if (tree_phi) {
                 // phi_(g,u) = sum_m w_m psi_(g,m,u): the m index occupies lane
-                // bits 2 .. 1 + log2 N, summed by a butterfly within the wave
+                // bits 2 .. 1 + log2 N; rows of 16 lanes first (DPP), then
+                // across rows
                 double wx = (t < n) ? s_w[(t >> 2) % N] * xs[0] : 0.0;
-                for (int off = 2 * N; off >= 4; off >>= 1) wx += __shfl_xor(wx, off, 64);
+                int off = 4;
+                if (N >= 4) {
+                    wx += dpp_f64<kDppRor4>(wx);
+                    wx += dpp_f64<kDppRor8>(wx);
+                    off = 16;
+                }
+                for (; off <= 2 * N; off <<= 1) wx += __shfl_xor(wx, off, 64);
                 if (live && t < n && (t >> 2) % N == 0) {
                     const int fi = (t / (4 * N)) * 4 + (t & 3);
                     const double f0 = Lf[fi];
-                    Lf[fi] = wx;
+                    Nf[fi] = wx;
                     if (S.norm == 0) dsq += (wx - f0) * (wx - f0);
                 }
             } else {
@@ -902,13 +1043,14 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                     const int i = t + r * TPC;
                     s_wx[cl][i] = (i < n ? s_w[(i >> 2) % N] : 0.0) * xs[r];
                 }
-                __syncthreads();
+                if constexpr (DB) wave_sync();
+                else __syncthreads();
                 if (live && t < 4 * G) {
                     const int g = t >> 2, u = t & 3;
                     double f = 0.0;
                     for (int m = 0; m < N; ++m) f += s_wx[cl][(g * N + m) * 4 + u];
                     const double f0 = Lf[t];
-                    Lf[t] = f;
+                    Nf[t] = f;
                     if (S.norm == 0) dsq += (f - f0) * (f - f0);
                 }
             }
@@ -916,19 +1058,77 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             if (tile + 1 < tile1) __syncthreads();   // s_vec / s_wx are reused by the next tile
         }
 
-        // (5) the partial of iteration l, once this workgroup's stores (the
-        // published edges and the slots it emptied) have completed
+        // (5) the partial of iteration l (the edges just published need not
+        // have completed: their readers wait on the slots themselves)
         {
-            const double v = wave_sum(dsq_acc);
-            if ((tid & 63) == 0) s_part[tid >> 6] = v;
+            const double v = wave_sum_dpp(dsq_acc);
+            if ((tid_o & 63) == 0) s_part[l & 1][tid_o >> 6] = v;
         }
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if (DB && lp >= 0) {
+            // this wave's share of the partials of iteration lp
+            double v = 0.0;
+            int tq = tid;
+            asm volatile("" : "+v"(tq));
+            bool on;
+            const int q0 = qslot(tq, &on);
+            if (on) {
+                v = wait_part(qv, q0);
+                for (int k = (tq & 63) + 64; k < Sw && (tq >> 6) * Sw + k < (int)nwg; k += 64)
+                    v += wait_part(ld_bits(part_prev + (tq >> 6) * Sw + k), (tq >> 6) * Sw + k);
+            }
+            if (bad) {
+                __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                v = __builtin_nan("");
+            }
+            v = wave_sum_dpp(v);
+            if ((tid_o & 63) == 0) s_psum[l & 1][tid_o >> 6] = v;
+        }
         __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
+        if (DB && lp >= 0) {
+            // the stopping rule (section 2.1) on e_(lp+1), identically in
+            // every thread of every workgroup; on a stop Psi^(lp+1) = Psi^(l-1)
+            // is intact in its LDS copy
+            double tot = 0.0;
 #pragma unroll
-            for (int w = 0; w < BS / 64; ++w) s += s_part[w];
-            st_bits(part_bits + (size_t)(l & 1) * nwg + wg, part_encode(s, l));
+            for (int w = 0; w < W; ++w) tot += s_psum[l & 1][w];
+            const int iters = lp + 1;
+            const double e = sqrt(tot);
+            const double rho = iters >= 2 ? e / s_eprev[(l + 1) & 1] : __builtin_nan("");
+            int done = 0, status = OK;
+            if (!isfinite(e)) { done = 1; status = NONFINITE; }
+            else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
+            else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - rho))) done = 1;
+            else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
+            if (tid_o == 0) {
+                s_eprev[l & 1] = e;
+                s_dec[l & 1][1] = status;
+                s_dec[l & 1][3] = rho;
+            }
+            if (done) {
+                // (thread 0 reads back what it wrote: the values need no registers meanwhile)
+                finish(s_eprev[l & 1], s_dec[l & 1][3], (int)s_dec[l & 1][1]);
+                return;
+            }
+        }
+        if (tid_o < 64) {
+            // wave 0 adds the W wave sums (lanes 0 .. W-1, a DPP row sum)
+            double s = (tid_o < W) ? s_part[l & 1][tid_o] : 0.0;
+            s += dpp_f64<kDppXor1>(s);
+            s += dpp_f64<kDppXor2>(s);
+            s += dpp_f64<kDppHalfMirror>(s);
+            s += dpp_f64<kDppMirror>(s);
+            if (tid_o == 0) st_bits(part_bits + (size_t)(l & 3) * nwg + wg, part_encode(s, l));
+        }
+        // one copy: the decision wave loads the partials it decides on next time
+        {
+            const int lq = l + 1 - LAG;
+            const bool dq = !DB && (tid_o >> 6) == dec_wave && lq >= 0;
+            const uint64_t *pq = part_bits + (size_t)(lq & 3) * nwg;
+#pragma unroll
+            for (int r = 0; r < PV; ++r) {
+                const int k = (tid_o & 63) + 64 * r;
+                pv[r] = (dq && k < (int)nwg) ? ld_bits(pq + k) : kSlotEmpty;
+            }
         }
     }
 }
@@ -1341,7 +1541,7 @@ hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, h
         hipLaunchKernelGGL(k_broadcast_state, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S);
     }
     size_t tot = (size_t)S.J * S.G * 4;
-    const size_t nex = (size_t)4 * local_nwg * S.N * S.G;
+    const size_t nex = (size_t)8 * local_nwg * S.N * S.G;
     if (nex > tot) tot = nex;
     hipLaunchKernelGGL(k_phi0, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S, local_nwg);
     return hipGetLastError();
