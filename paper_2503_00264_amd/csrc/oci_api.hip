@@ -184,7 +184,7 @@ static Layout layout(const oci_desc *d, int num_cu) {
     L.alpha = take(J * G * N * 2 * 8);
     L.ein = take(J * G * N * 2 * 8);
     const size_t si_blocks = (J * G * 4 + kBlock - 1) / kBlock;
-    size_t parts = (size_t)num_cu * 8 * 4;   // [4][max workgroups]: the local kernel cycles four
+    size_t parts = (size_t)num_cu * 8 * kPartSlots;   // the local kernel's ring of partial sums
     if (si_blocks > parts) parts = si_blocks;
     L.part = take(parts * 8);
     L.total = o;
@@ -222,8 +222,8 @@ static int configure(oci_handle *h, int block, bool allow_local, bool allow_res,
     bool local = false, res = false;
     long nwg = 0;
     size_t dyn_lds = 0;
-    // dynamic LDS of the local kernel: cells x (n + 4G) (three times with
-    // resident rows) + tiles x 2NG doubles
+    // dynamic LDS of the local kernel: cells x (n + 4G) (kResidentCopies
+    // times with resident rows) + tiles x 2NG doubles
     auto try_local = [&](bool r) -> bool {
         size_t stat = 0;
         if (local_static_lds(h->fp32, h->np, r, block, &stat) != hipSuccess) return false;
@@ -234,8 +234,8 @@ static int configure(oci_handle *h, int block, bool allow_local, bool allow_res,
         if (w > wg_cap) w = wg_cap;
         for (int it = 0; it < 8 && w >= 1; ++it) {
             const long tpw = (ntiles + w - 1) / w;
-            // resident rows keep three copies of the range's Psi and phi
-            const size_t dyn = ((size_t)(r ? 3 : 1) * tpw * cpt * (h->n + 4 * G) + (size_t)tpw * 2 * N * G) * 8;
+            // resident rows keep kResidentCopies copies of the range's Psi and phi
+            const size_t dyn = ((size_t)(r ? kResidentCopies : 1) * tpw * cpt * (h->n + 4 * G) + (size_t)tpw * 2 * N * G) * 8;
             if (stat + dyn > lds_max) return false;
             int o = 0;
             if (local_occupancy(h->fp32, h->np, r, block, dyn, &o) != hipSuccess || o < 1) return false;

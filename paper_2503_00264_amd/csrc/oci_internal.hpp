@@ -24,6 +24,17 @@ constexpr int kBarGroup = 16;
 // 2^kPartTagBits; kSlotEmpty (sign bit set) never matches a tag either.
 constexpr uint64_t kSlotEmpty = ~0ull;
 constexpr int kPartTagBits = 4;
+// Partial-sum slots per workgroup (a ring over iterations) and, with
+// register-resident rows, how many iterations behind the partials read for a
+// decision are; that decision takes effect one iteration later still, so the
+// kernel keeps kResidentCopies = kResidentLag + 2 LDS copies of the range's
+// iterate.  A slot is rewritten kPartSlots iterations later, which needs
+// kPartSlots > kResidentLag + 1; the tag period 2^kPartTagBits exceeds
+// kPartSlots.
+constexpr int kPartSlots = 8;
+constexpr int kResidentLag = 2;
+constexpr int kResidentCopies = kResidentLag + 2;
+static_assert(kPartSlots > kResidentLag + 1 && (1 << kPartTagBits) > kPartSlots, "partial-sum ring");
 
 // Control block of one slab problem, in the workspace.  Written by the step
 // kernels only; the host reads `done` to learn that a step has stopped.
@@ -67,7 +78,7 @@ struct Slab {
     double *si_msw;              // [J][NG][4] 2x2 edge-to-edge map, in sweep order
     double *si_alpha;            // [J][NG][2] outgoing edges of the uncoupled solution, sweep order
     double *si_ein;              // [J][NG][2] incident edges met by the sweep, sweep order
-    double *partials;            // [4][max workgroups] per-workgroup sums (by iteration mod 2, or mod 4)
+    double *partials;            // [kPartSlots][max workgroups] per-workgroup sums (by iteration mod 2, or mod kPartSlots)
     Ctl *ctl;
     // grid barrier words, 256 bytes apart: [0] arrivals of group leaders,
     // [kBarStride] release flag, [(2 + k) * kBarStride] arrivals in group k

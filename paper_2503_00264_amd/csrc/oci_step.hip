@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_phi0(Slab S, int nwg) {
     if (t < (size_t)S.J * S.G * 4) phi0_elem(S, t);
     const size_t nex = (size_t)8 * nwg * S.N * S.G;
     if (t < nex) reinterpret_cast<uint64_t *>(S.exch)[t] = kSlotEmpty;
-    if (t < (size_t)4 * nwg) reinterpret_cast<uint64_t *>(S.partials)[t] = kSlotEmpty;
+    if (t < (size_t)kPartSlots * nwg) reinterpret_cast<uint64_t *>(S.partials)[t] = kSlotEmpty;
 }
 
 // psi of the first iterate from the state (both time levels).
@@ -644,8 +644,8 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     constexpr bool DB = RES;
     static_assert(!DB || TPC <= 64, "resident rows: one cell per wave or less");
     static_assert(BS <= 1024, "wave sums are added within one row of 16 lanes");
-    constexpr int NCOPY = DB ? 3 : 1;   // LDS copies of Psi and phi
-    constexpr int LAG = DB ? 2 : 1;     // iteration l decides on e_(l - LAG + 1)
+    constexpr int LAG = DB ? kResidentLag : 1;   // iteration l decides on e_(l - LAG + 1)
+    constexpr int NCOPY = DB ? kResidentCopies : 1;   // LDS copies of Psi and phi
     constexpr int PV = 4;               // partial sums per lane loaded ahead of the decision
     constexpr bool WAVE_CELL = TPC <= 64;   // a cell's rows lie in one wave (then RPT = 1)
     typedef typename Vec16<T>::type VT;
@@ -754,7 +754,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
         double *N_psi = L_psi0 + (size_t)nb * ncell * n;
         double *N_phi = L_phi0 + (size_t)nb * ncell * 4 * G;
         const int lp = l - LAG;                          // iteration whose partials are decided on
-        const uint64_t *part_prev = part_bits + (size_t)(lp & 3) * nwg;
+        const uint64_t *part_prev = part_bits + (size_t)(lp & (kPartSlots - 1)) * nwg;
         const int par = (l + 1) & 1;                     // exchange parity this iteration publishes
         const bool dec = !DB && (tid_o >> 6) == dec_wave && lp >= 0;   // this wave decides (wave-uniform)
         double dsq_acc = 0.0;
@@ -817,9 +817,8 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                 s_dec[l & 1][3] = rho;
             }
         };
-        // After a stop: the final iterate Psi^(lp+1) and its flux leave LDS.
-        auto finish = [&](double e, double rho, int status) {
-            const int iters = lp + 1;
+        // After a stop: the final iterate Psi^(iters) and its flux leave LDS.
+        auto finish = [&](int iters, double e, double rho, int status) {
             const int fin = (base + iters) & 1;
             const int db = iters % NCOPY;
             const double *D_psi = L_psi0 + (size_t)db * ncell * n;
@@ -968,7 +967,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             } else {
                 __syncthreads();   // s_vec and the decision complete; every read of this tile's Psi^(l) is done
                 if (tile == tile0 && lp >= 0 && s_dec[l & 1][0] != 0.0) {
-                    finish(s_dec[l & 1][2], s_dec[l & 1][3], (int)s_dec[l & 1][1]);
+                    finish(lp + 1, s_dec[l & 1][2], s_dec[l & 1][3], (int)s_dec[l & 1][1]);
                     return;
                 }
             }
@@ -1084,30 +1083,38 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             if ((tid_o & 63) == 0) s_psum[l & 1][tid_o >> 6] = v;
         }
         __syncthreads();
-        if (DB && lp >= 0) {
-            // the stopping rule (section 2.1) on e_(lp+1), identically in
-            // every thread of every workgroup; on a stop Psi^(lp+1) = Psi^(l-1)
-            // is intact in its LDS copy
-            double tot = 0.0;
-#pragma unroll
-            for (int w = 0; w < W; ++w) tot += s_psum[l & 1][w];
-            const int iters = lp + 1;
-            const double e = sqrt(tot);
-            const double rho = iters >= 2 ? e / s_eprev[(l + 1) & 1] : __builtin_nan("");
-            int done = 0, status = OK;
-            if (!isfinite(e)) { done = 1; status = NONFINITE; }
-            else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
-            else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - rho))) done = 1;
-            else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
-            if (tid_o == 0) {
-                s_eprev[l & 1] = e;
-                s_dec[l & 1][1] = status;
-                s_dec[l & 1][3] = rho;
-            }
-            if (done) {
-                // (thread 0 reads back what it wrote: the values need no registers meanwhile)
-                finish(s_eprev[l & 1], s_dec[l & 1][3], (int)s_dec[l & 1][1]);
+        if (DB) {
+            // the decision wave took the decision on the partials of
+            // iteration l - 1 - LAG after the previous barrier; it applies
+            // now, when every wave sees it (on a stop that iterate,
+            // Psi^(l-LAG), is intact in its LDS copy)
+            if (l - 1 - LAG >= 0 && s_dec[(l + 1) & 1][0] != 0.0) {
+                finish(l - LAG, s_dec[(l + 1) & 1][2], s_dec[(l + 1) & 1][3], (int)s_dec[(l + 1) & 1][1]);
                 return;
+            }
+            if (lp >= 0 && (tid_o >> 6) == dec_wave) {
+                // the stopping rule (section 2.1) on e_(lp+1) from the shares
+                // every wave left before the barrier, in the decision wave
+                // only (every workgroup's decision wave adds the same values in
+                // the same order)
+                double tot = 0.0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) tot += s_psum[l & 1][w];
+                const int iters = lp + 1;
+                const double e = sqrt(tot);
+                const double rho = iters >= 2 ? e / s_eprev[(l + 1) & 1] : __builtin_nan("");
+                int done = 0, status = OK;
+                if (!isfinite(e)) { done = 1; status = NONFINITE; }
+                else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
+                else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - rho))) done = 1;
+                else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
+                if ((tid_o & 63) == 0) {
+                    s_eprev[l & 1] = e;
+                    s_dec[l & 1][0] = done;
+                    s_dec[l & 1][1] = status;
+                    s_dec[l & 1][2] = e;
+                    s_dec[l & 1][3] = rho;
+                }
             }
         }
         if (tid_o < 64) {
@@ -1117,13 +1124,13 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             s += dpp_f64<kDppXor2>(s);
             s += dpp_f64<kDppHalfMirror>(s);
             s += dpp_f64<kDppMirror>(s);
-            if (tid_o == 0) st_bits(part_bits + (size_t)(l & 3) * nwg + wg, part_encode(s, l));
+            if (tid_o == 0) st_bits(part_bits + (size_t)(l & (kPartSlots - 1)) * nwg + wg, part_encode(s, l));
         }
         // one copy: the decision wave loads the partials it decides on next time
         {
             const int lq = l + 1 - LAG;
             const bool dq = !DB && (tid_o >> 6) == dec_wave && lq >= 0;
-            const uint64_t *pq = part_bits + (size_t)(lq & 3) * nwg;
+            const uint64_t *pq = part_bits + (size_t)(lq & (kPartSlots - 1)) * nwg;
 #pragma unroll
             for (int r = 0; r < PV; ++r) {
                 const int k = (tid_o & 63) + 64 * r;
