@@ -759,13 +759,18 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
         const bool dec = !DB && (tid_o >> 6) == dec_wave && lp >= 0;   // this wave decides (wave-uniform)
         double dsq_acc = 0.0;
         int bad = 0;
-        // three copies: this wave's share of the partials of iteration lp,
-        // slots [w Sw, (w + 1) Sw), one per lane (more past 64 lanes)
+        // resident rows: this wave's share of the partials of iteration lp,
+        // slots [s Sw, (s + 1) Sw) for share s, one per lane (more past 64
+        // lanes); the first and the last wave (the range's end cells, on the
+        // critical path) hold no share when there are four waves or more
         constexpr int W = BS / 64;
-        const int Sw = ((int)nwg + W - 1) / W;
+        constexpr int WS0 = W >= 4 ? 1 : 0;       // wave of share 0
+        constexpr int WSN = W >= 4 ? W - 2 : W;   // waves holding a share
+        const int Sw = ((int)nwg + WSN - 1) / WSN;
         auto qslot = [&](int tq, bool *on) -> int {   // (re-derived where needed, to spare registers)
-            const int q = (tq >> 6) * Sw + (tq & 63);
-            *on = DB && lp >= 0 && (tq & 63) < Sw && q < (int)nwg;
+            const int sh = (tq >> 6) - WS0;
+            const int q = sh * Sw + (tq & 63);
+            *on = DB && lp >= 0 && sh >= 0 && sh < WSN && (tq & 63) < Sw && q < (int)nwg;
             return q;
         };
         uint64_t qv = kSlotEmpty;
@@ -978,11 +983,14 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             for (int r = 0; r < RPT; ++r) acc[r] = T(0);
             if (live) {
                 if constexpr (RES) {
+                    // four partial sums, so the FMA chain is a quarter as long
+                    T a4[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
                     for (int kv = 0; kv < NV; ++kv) {
                         const VT bv = *reinterpret_cast<const VT *>(&s_vec[cl][kv * V]);
-                        acc[0] += dot16(xr[kv], bv);
+                        a4[kv & 3] += dot16(xr[kv], bv);
                     }
+                    acc[0] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
                 } else {
                     const T *Xc = Xall + (size_t)j * NP * NP;
 #pragma unroll 8
@@ -1071,9 +1079,10 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             bool on;
             const int q0 = qslot(tq, &on);
             if (on) {
+                const int b0 = q0 - (tq & 63);   // first slot of this wave's share
                 v = wait_part(qv, q0);
-                for (int k = (tq & 63) + 64; k < Sw && (tq >> 6) * Sw + k < (int)nwg; k += 64)
-                    v += wait_part(ld_bits(part_prev + (tq >> 6) * Sw + k), (tq >> 6) * Sw + k);
+                for (int k = (tq & 63) + 64; k < Sw && b0 + k < (int)nwg; k += 64)
+                    v += wait_part(ld_bits(part_prev + b0 + k), b0 + k);
             }
             if (bad) {
                 __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1136,6 +1145,363 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                 const int k = (tid_o & 63) + 64 * r;
                 pv[r] = (dq && k < (int)nwg) ? ld_bits(pq + k) : kSlotEmpty;
             }
+        }
+    }
+}
+
+// Register-resident OCI kernel (FP32 n <= 64, FP64 n <= 32): one tile of
+// CPT cells per workgroup (launched with nwg = ntiles), one cell per wave or
+// less, each thread holding its row of the cell's inverse in VGPRs for the
+// whole step.  The step is bound by instruction issue (four waves share a
+// SIMD), so everything that does not change between iterations is prepared
+// once: each lane's row coordinates and roles packed in one register, the
+// constant part of b with the boundary sources folded in, the 4x4 corner
+// coefficients and the scattering block (LDS).  Per iteration a wave runs its
+// cells on its own (steps 1-4, ordered within the wave only), then all waves
+// meet once at a workgroup barrier.  Edges cross workgroups through the tagged
+// slots; the stopping decision works as in k_oci_local with three copies of
+// the iterate's predecessors in LDS (kResidentCopies in all): every wave other
+// than the two end ones adds a share of the partials of iteration l - LAG
+// before the barrier, one wave applies the rule after it, and the outcome
+// takes effect at the next barrier.
+namespace res {
+enum : int {
+    LIVE = 1 << 18,    // a row of a live cell (t < n, j < J)
+    INL = 1 << 19,     // receives an edge from the left (mu > 0, u even)
+    INR = 1 << 20,     // receives an edge from the right (mu < 0, u odd)
+    BND = 1 << 21,     // ... from the slab boundary (folded into the constant part of b)
+    EXT = 1 << 22,     // ... from a neighbour workgroup
+    OUTL = 1 << 23,    // its new value goes to the left neighbour workgroup
+    OUTR = 1 << 24,    // ... to the right neighbour workgroup
+    PHI = 1 << 25,     // writes phi_(g,u) (m = 0)
+    CELL = 1 << 26,    // the lane's cell is live (j < J)
+};
+}
+
+template <typename T, int NP, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
+void k_oci_res(Slab S, StepIO io, int ntiles) {
+    constexpr bool REF = sizeof(T) == 4;
+    static_assert(NP <= 64 && NP >= 8, "one cell per wave or less");
+    static_assert(BS <= 1024, "wave sums are added within one row of 16 lanes");
+    constexpr int TPC = NP;
+    constexpr int LOGT = NP == 8 ? 3 : NP == 16 ? 4 : NP == 32 ? 5 : 6;
+    constexpr int CPT = BS / TPC;
+    constexpr int W = BS / 64;
+    constexpr int V = 16 / sizeof(T);
+    constexpr int NV = NP / V;
+    constexpr int LAG = kResidentLag;
+    constexpr int NCOPY = kResidentCopies;
+    typedef typename Vec16<T>::type VT;
+    (void)ntiles;
+
+    extern __shared__ __align__(16) double s_dyn[];
+    __shared__ __align__(16) T s_vec[CPT][NP];
+    __shared__ __align__(16) double s_coef[REF ? CPT : 1][REF ? NP : 1][4];
+    __shared__ double s_crow[CPT][NP];
+    __shared__ double s_scat[REF ? CPT : 1][REF ? NP * NP / 64 : 1];   // G*G <= NP*NP/64
+    __shared__ double s_wx[CPT][NP];
+    __shared__ double s_mu[NP / 4], s_w[NP / 4];
+    __shared__ double s_part[2][W], s_psum[2][W], s_dec[2][4], s_eprev[2];
+
+    const int tid = threadIdx.x;
+    const int J = S.J, N = S.N, G = S.G, n = S.n, nh = S.N / 2, NG = S.N * S.G;
+    const unsigned nwg = gridDim.x;
+    const int wg = blockIdx.x;
+    const int c0 = wg * CPT;
+    const int c1 = min(c0 + CPT, J);
+    double *L_psi0 = s_dyn;                                  // [NCOPY][CPT][n]
+    double *L_phi0 = L_psi0 + (size_t)NCOPY * CPT * n;       // [NCOPY][CPT][4G]
+    uint64_t *exch_bits = reinterpret_cast<uint64_t *>(S.exch);
+    auto exq = [&](int par, int w, int side, int lev, int g, int mm) -> uint64_t * {
+        return exch_bits + 2 * ((((size_t)par * nwg + w) * 2 + side) * NG + ((size_t)lev * G + g) * nh + mm);
+    };
+
+    for (int m = tid; m < N; m += BS) { s_mu[m] = S.mu[m]; s_w[m] = S.w[m]; }
+    __syncthreads();
+
+    // per-lane row coordinates and roles
+    int rinfo = 0;
+    {
+        const int cl = tid >> LOGT, t = tid & (TPC - 1), j = c0 + cl;
+        if (j < J) rinfo |= res::CELL;
+        if (j < J && t < n) {
+            const int g = t / (4 * N), m = (t >> 2) % N, u = t & 3;
+            rinfo |= m | (g << 8) | (u << 16) | res::LIVE;
+            if (m == 0) rinfo |= res::PHI;
+            if (m >= nh && !(u & 1)) {
+                rinfo |= res::INL;
+                if (j == 0) rinfo |= res::BND;
+                else if (j == c0) rinfo |= res::EXT;
+            }
+            if (m < nh && (u & 1)) {
+                rinfo |= res::INR;
+                if (j == J - 1) rinfo |= res::BND;
+                else if (j == c1 - 1) rinfo |= res::EXT;
+            }
+            if (j == c0 && wg > 0 && m < nh && !(u & 1)) rinfo |= res::OUTL;
+            if (j == c1 - 1 && c1 < J && m >= nh && (u & 1)) rinfo |= res::OUTR;
+        }
+    }
+
+    // the inverse rows into registers; the iterate, its flux and the step's
+    // constants into LDS
+    const T *Xall = reinterpret_cast<const T *>(S.X);
+    VT xr[NV];
+    {
+        const int cl = tid >> LOGT, t = tid & (TPC - 1), j = c0 + cl;
+#pragma unroll
+        for (int kv = 0; kv < NV; ++kv) xr[kv] = VT{};
+        if (rinfo & res::CELL) {
+            const T *Xc = Xall + (size_t)j * NP * NP;
+#pragma unroll
+            for (int kv = 0; kv < NV; ++kv) xr[kv] = *reinterpret_cast<const VT *>(Xc + ((size_t)kv * NP + t) * V);
+        }
+        if (rinfo & res::LIVE) {
+            const int m = rinfo & 0xFF, g = (rinfo >> 8) & 0xFF, u = (rinfo >> 16) & 3, lev = u >> 1;
+            const double mu = s_mu[m];
+            double b = S.crhs[(size_t)j * n + t];
+            if ((rinfo & res::INL) && (rinfo & res::BND) && io.inc_l)
+                b += mu * io.inc_l[((size_t)lev * G + g) * nh + (m - nh)];
+            if ((rinfo & res::INR) && (rinfo & res::BND) && io.inc_r)
+                b -= mu * io.inc_r[((size_t)lev * G + g) * nh + m];
+            s_crow[cl][t] = b;
+            if constexpr (REF) lc_row(S, j, g, mu, u, s_coef[cl][t]);
+        }
+        if constexpr (REF)
+            if ((rinfo & res::CELL) && t < G * G) s_scat[cl][t] = 0.25 * S.dx[j] * S.sigma_s[(size_t)j * G * G + t];
+    }
+    const int base = S.ctl->base;
+    const double *__restrict__ psi_g = S.psi[base];   // the iterate in global memory: only read at l = 0
+    {
+        const double *pin = psi_g + (size_t)c0 * n;
+        const int tot = (c1 - c0) * n;
+        for (int k = tid; k < tot; k += BS) L_psi0[k] = pin[k];
+        const double *fin = S.phi[base] + (size_t)c0 * 4 * G;
+        const int totf = (c1 - c0) * 4 * G;
+        for (int k = tid; k < totf; k += BS) L_phi0[k] = fin[k];
+    }
+    __syncthreads();
+
+    const bool tree_phi = (N & (N - 1)) == 0;
+    uint64_t *part_bits = reinterpret_cast<uint64_t *>(S.partials);
+    // shares of the partial sums: waves WS0 .. WS0 + WSN - 1 (not the two end
+    // waves, which carry the range's end cells, when there are four or more)
+    constexpr int WS0 = W >= 4 ? 1 : 0;
+    constexpr int WSN = W >= 4 ? W - 2 : W;
+    const int Sw = ((int)nwg + WSN - 1) / WSN;
+    const int dec_wave = W / 2;
+
+    for (int l = 0;; ++l) {
+        // re-derived every iteration from opaque copies, so the compiler keeps
+        // no per-lane addresses live across the loop (registers)
+        int ri = rinfo, tq = tid;
+        asm volatile("" : "+v"(ri), "+v"(tq));
+        const int cl = tq >> LOGT, t = tq & (TPC - 1);
+        const int m = ri & 0xFF, g = (ri >> 8) & 0xFF, u = (ri >> 16) & 3;
+        const unsigned cb = (unsigned)l % NCOPY, nb = ((unsigned)l + 1) % NCOPY;
+        const double *Lp = L_psi0 + ((size_t)cb * CPT + cl) * n;   // this cell's Psi^(l)
+        const double *Lf = L_phi0 + ((size_t)cb * CPT + cl) * 4 * G;
+        double *Np = L_psi0 + ((size_t)nb * CPT + cl) * n;         // ... and Psi^(l+1)
+        double *Nf = L_phi0 + ((size_t)nb * CPT + cl) * 4 * G;
+        const int lp = l - LAG;                                   // iteration whose partials this one adds
+        const uint64_t *part_prev = part_bits + (size_t)(lp & (kPartSlots - 1)) * nwg;
+        int bad = 0;
+
+        // this wave's share of the partials of iteration lp, loaded now and
+        // added before the barrier
+        const int sh = (tq >> 6) - WS0;
+        const int q0 = sh * Sw + (tq & 63);
+        const bool qon = lp >= 0 && sh >= 0 && sh < WSN && (tq & 63) < Sw && q0 < (int)nwg;
+        const uint64_t qv = qon ? ld_bits(part_prev + q0) : kSlotEmpty;
+
+        // (1) b = constant part + lagged incident edge from a cell
+        double xold = 0.0, b = 0.0;
+        if (ri & res::LIVE) {
+            xold = Lp[t];
+            b = s_crow[cl][t];
+            if ((ri & (res::INL | res::INR)) && !(ri & res::BND)) {
+                const double mu = s_mu[m];
+                const int lev = u >> 1;
+                double e;
+                // upwind incident term: + mu psi_(j-1,R) for mu > 0, - mu psi_(j+1,L) for mu < 0
+                if (ri & res::INL) {
+                    if (!(ri & res::EXT)) e = Lp[t - n + 1];
+                    else if (l == 0) e = psi_g[(size_t)(c0 - 1) * n + t + 1];
+                    else e = take_edge(exq(l & 1, wg - 1, 1, lev, g, m - nh), l, &bad);
+                    b += mu * e;
+                } else {
+                    if (!(ri & res::EXT)) e = Lp[t + n - 1];
+                    else if (l == 0) e = psi_g[(size_t)c1 * n + t - 1];
+                    else e = take_edge(exq(l & 1, wg + 1, 0, lev, g, m), l, &bad);
+                    b -= mu * e;
+                }
+            }
+        }
+        if (bad) __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+        int expo = 0;
+        if constexpr (REF) {
+            // (2) FP64 residual r = b - A_j Psi^(l), matrix-free, scaled by
+            // the power of two of its largest entry in the cell
+            double r = 0.0;
+            if (ri & res::LIVE) {
+                const double2 ca = *reinterpret_cast<const double2 *>(&s_coef[cl][t][0]);
+                const double2 cc = *reinterpret_cast<const double2 *>(&s_coef[cl][t][2]);
+                const double2 pa = *reinterpret_cast<const double2 *>(Lp + (t & ~3));
+                const double2 pc = *reinterpret_cast<const double2 *>(Lp + (t & ~3) + 2);
+                double sc = 0.0;
+                for (int gp = 0; gp < G; ++gp) sc += s_scat[cl][g * G + gp] * Lf[gp * 4 + u];
+                r = b - (ca.x * pa.x + ca.y * pa.y + cc.x * pc.x + cc.y * pc.y) + sc;
+            }
+            int ex = (int)(((uint64_t)__double_as_longlong(r) >> 52) & 0x7FF);
+            ex = seg_max_i32<TPC>(ex);
+            if (ex > 0 && ex < 0x7FF) expo = ex - 1022;
+            s_vec[cl][t] = (T)ldexp(r, -expo);
+        } else {
+            s_vec[cl][t] = (T)b;
+        }
+        wave_sync();   // the cell's s_vec is complete (the cell is this wave's)
+
+        // (3) apply the inverse (four partial sums: a quarter of the FMA chain)
+        T a4[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int kv = 0; kv < NV; ++kv) {
+            const VT bv = *reinterpret_cast<const VT *>(&s_vec[cl][kv * V]);
+            a4[kv & 3] += dot16(xr[kv], bv);
+        }
+        const T acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+
+        // (4) new iterate (the range's two end edges also go to the
+        // neighbours), scalar flux and its change
+        const double x = REF ? xold + ldexp((double)acc, expo) : (double)acc;
+        double dsq = 0.0;
+        if (ri & res::LIVE) {
+            Np[t] = x;
+            if (S.norm == 1) dsq = (x - xold) * (x - xold);
+            const int par = (l + 1) & 1;
+            if (ri & res::OUTL) put_edge(exq(par, wg, 0, u >> 1, g, m), x, l + 1);
+            if (ri & res::OUTR) put_edge(exq(par, wg, 1, u >> 1, g, m - nh), x, l + 1);
+        }
+        if (tree_phi) {
+            // phi_(g,u) = sum_m w_m psi_(g,m,u): m occupies lane bits 2 ..
+            // 1 + log2 N; rows of 16 lanes first (DPP), then across rows
+            double wx = (ri & res::LIVE) ? s_w[m] * x : 0.0;
+            int off = 4;
+            if (N >= 4) {
+                wx += dpp_f64<kDppRor4>(wx);
+                wx += dpp_f64<kDppRor8>(wx);
+                off = 16;
+            }
+            for (; off <= 2 * N; off <<= 1) wx += __shfl_xor(wx, off, 64);
+            if (ri & res::PHI) {
+                const int fi = g * 4 + u;
+                const double f0 = Lf[fi];
+                Nf[fi] = wx;
+                if (S.norm == 0) dsq += (wx - f0) * (wx - f0);
+            }
+        } else {
+            s_wx[cl][t] = (ri & res::LIVE) ? s_w[m] * x : 0.0;
+            wave_sync();
+            if ((ri & res::CELL) && t < 4 * G) {
+                const int gg = t >> 2, uu = t & 3;
+                double f = 0.0;
+                for (int mm = 0; mm < N; ++mm) f += s_wx[cl][(gg * N + mm) * 4 + uu];
+                const double f0 = Lf[t];
+                Nf[t] = f;
+                if (S.norm == 0) dsq += (f - f0) * (f - f0);
+            }
+        }
+
+        // (5) this wave's sum of squared changes and its share of the
+        // partials of iteration lp, then the barrier
+        {
+            const double v = wave_sum_dpp(dsq);
+            if ((tid & 63) == 0) s_part[l & 1][tid >> 6] = v;
+        }
+        if (lp >= 0) {
+            double v = 0.0;
+            if (qon) {
+                auto wait_part = [&](uint64_t xq, int k) -> double {
+                    long spins = 0;
+#pragma clang loop unroll(disable)
+                    while (!part_ready(xq, lp)) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (++spins > kSpinLimit) { bad = 1; break; }
+                        xq = ld_bits(part_prev + k);
+                    }
+                    return part_value(xq);
+                };
+                const int b0 = q0 - (tid & 63);
+                v = wait_part(qv, q0);
+                for (int k = (tid & 63) + 64; k < Sw && b0 + k < (int)nwg; k += 64)
+                    v += wait_part(ld_bits(part_prev + b0 + k), b0 + k);
+            }
+            if (bad) {
+                __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                v = __builtin_nan("");
+            }
+            v = wave_sum_dpp(v);
+            if ((tid & 63) == 0) s_psum[l & 1][tid >> 6] = v;
+        }
+        __syncthreads();
+
+        // the decision taken after the previous barrier applies now; on a
+        // stop the iterate it concerns, Psi^(l-LAG), is intact in its copy
+        if (l - 1 - LAG >= 0 && s_dec[(l + 1) & 1][0] != 0.0) {
+            const int iters = l - LAG;
+            const int fin = (base + iters) & 1;
+            const double *D_psi = L_psi0 + (size_t)((unsigned)iters % NCOPY) * CPT * n;
+            const double *D_phi = L_phi0 + (size_t)((unsigned)iters % NCOPY) * CPT * 4 * G;
+            double *pout = S.psi[fin] + (size_t)c0 * n;
+            const int totp = (c1 - c0) * n;
+            for (int k = tid; k < totp; k += BS) pout[k] = D_psi[k];
+            double *fout = S.phi[fin] + (size_t)c0 * 4 * G;
+            const int totf = (c1 - c0) * 4 * G;
+            for (int k = tid; k < totf; k += BS) fout[k] = D_phi[k];
+            if (wg == 0 && tid == 0) {
+                Ctl *c = S.ctl;
+                c->iter = iters;
+                c->e_last = s_dec[(l + 1) & 1][2];
+                c->rho = s_dec[(l + 1) & 1][3];
+                c->e_prev = s_dec[(l + 1) & 1][2];
+                c->status = (int)s_dec[(l + 1) & 1][1];
+                c->done = 1;
+            }
+            return;
+        }
+        if (lp >= 0 && (tid >> 6) == dec_wave) {
+            // the stopping rule (section 2.1) on e_(lp+1), from the shares
+            // (every workgroup's decision wave adds the same values in the
+            // same order)
+            double tot = 0.0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) tot += s_psum[l & 1][w];
+            const int iters = lp + 1;
+            const double e = sqrt(tot);
+            const double rho = iters >= 2 ? e / s_eprev[(l + 1) & 1] : __builtin_nan("");
+            int done = 0, status = OK;
+            if (!isfinite(e)) { done = 1; status = NONFINITE; }
+            else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
+            else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - rho))) done = 1;
+            else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
+            if ((tid & 63) == 0) {
+                s_eprev[l & 1] = e;
+                s_dec[l & 1][0] = done;
+                s_dec[l & 1][1] = status;
+                s_dec[l & 1][2] = e;
+                s_dec[l & 1][3] = rho;
+            }
+        }
+        if (tid < 64) {
+            // wave 0 publishes the workgroup's partial of iteration l (the
+            // W wave sums added in a DPP row)
+            double s = (tid < W) ? s_part[l & 1][tid] : 0.0;
+            s += dpp_f64<kDppXor1>(s);
+            s += dpp_f64<kDppXor2>(s);
+            s += dpp_f64<kDppHalfMirror>(s);
+            s += dpp_f64<kDppMirror>(s);
+            if (tid == 0) st_bits(part_bits + (size_t)(l & (kPartSlots - 1)) * nwg + wg, part_encode(s, l));
         }
     }
 }
@@ -1459,10 +1825,18 @@ static hipError_t dispatch(bool fp32, int np, bool res, int bs, F f) {
     return bs == 1024 ? by_np<double, false, 1024>(np, f) : by_np<double, false, 256>(np, f);
 }
 
+// The workgroup-local kernel of a launch shape: register-resident rows run
+// k_oci_res, streamed rows k_oci_local.
+template <typename T, int NP, bool RES, int BS>
+static const void *local_kernel() {
+    if constexpr (RES) return (const void *)&k_oci_res<T, NP, BS>;
+    else return (const void *)&k_oci_local<T, NP, false, BS>;
+}
+
 template <typename T, int NP, bool RES, int BS>
 static hipError_t launch_local_t(const Slab &S, const StepIO &io, int nwg, int ntiles, size_t dyn, hipStream_t st) {
     if (RES && nwg != ntiles) return hipErrorInvalidValue;
-    const void *f = (const void *)&k_oci_local<T, NP, RES, BS>;
+    const void *f = local_kernel<T, NP, RES, BS>();
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
     void *args[] = {(void *)&S, (void *)&io, (void *)&ntiles};
@@ -1471,7 +1845,7 @@ static hipError_t launch_local_t(const Slab &S, const StepIO &io, int nwg, int n
 
 template <typename T, int NP, bool RES, int BS>
 static hipError_t occupancy_local_t(int *blocks, size_t dyn) {
-    const void *f = (const void *)&k_oci_local<T, NP, RES, BS>;
+    const void *f = local_kernel<T, NP, RES, BS>();
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, BS, dyn);
@@ -1480,7 +1854,7 @@ static hipError_t occupancy_local_t(int *blocks, size_t dyn) {
 template <typename T, int NP, bool RES, int BS>
 static size_t static_lds_local_t() {
     hipFuncAttributes a;
-    if (hipFuncGetAttributes(&a, (const void *)&k_oci_local<T, NP, RES, BS>) != hipSuccess) return (size_t)-1;
+    if (hipFuncGetAttributes(&a, local_kernel<T, NP, RES, BS>()) != hipSuccess) return (size_t)-1;
     return a.sharedSizeBytes;
 }
 
