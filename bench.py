@@ -66,8 +66,11 @@ def problems(name):
 
 def kernel_label(cfg, fp32, np_):
     t = "float" if fp32 else "double"
-    kind = "k_oci_local" if cfg["local"] else "k_oci_step"
-    return f"{kind}<{t},{np_},{'true' if cfg['resident'] else 'false'},{cfg['block']}>"
+    if cfg["local"] and cfg["resident"]:
+        return f"k_oci_res<{t},{np_},{cfg['block']}>"
+    if cfg["local"]:
+        return f"k_oci_local<{t},{np_},{cfg['block']}>"
+    return f"k_oci_step<{t},{np_},{'true' if cfg['resident'] else 'false'},{cfg['block']}>"
 
 
 def run_method(probs, method, precision, K, W_, tol, torch, B, autotune=True):

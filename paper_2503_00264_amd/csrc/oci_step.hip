@@ -603,28 +603,27 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Workgroup-local persistent OCI kernel.  Each workgroup owns the contiguous
-// cells [c0, c1) for the whole step and keeps their iterate Psi and scalar
-// flux phi in LDS (dynamic shared memory: [cells][n] Psi, [cells][4G] phi,
-// then per internal tile boundary a snapshot of the 2NG edge values that
-// cross it; with register-resident rows, one tile per workgroup and Psi and
-// phi three times, [3][cells][n] and [3][cells][4G]).  Only the edges at the
-// two ends of the range cross
-// workgroups, handed to the neighbour through tagged slots (put_edge /
-// take_edge); iterate 0's neighbour edges come from global memory (written by
-// earlier launches).  There is no grid barrier: a workgroup waits only for its
-// two neighbours' edges, and for the tagged partial sums it needs for the
-// stopping decision.  An edge slot is written again two iterations later,
-// and the writer cannot get there before the reader has taken the old value:
-// the writer's next iteration needs the reader's edges, which the reader only
-// publishes after that read.  A partial-sum slot (four of them, by iteration
-// mod 4) is written again four iterations later, after its writer has taken
-// a decision that needs every workgroup's partial of an iteration whose end
-// follows that workgroup's last read of the slot.  No store has to complete
-// before another is issued.  At the end the final Psi and phi are written to
-// global memory.
-// Template parameters as k_oci_step.
-template <typename T, int NP, bool RES, int BS>
+// Workgroup-local persistent OCI kernel with streamed inverse rows.  Each
+// workgroup owns the contiguous cells [c0, c1) (one or more tiles) for the
+// whole step and keeps their iterate Psi and scalar flux phi in LDS (dynamic
+// shared memory: [cells][n] Psi, [cells][4G] phi, then per internal tile
+// boundary a snapshot of the 2NG edge values that cross it).  Only the edges
+// at the two ends of the range cross workgroups, handed to the neighbour
+// through tagged slots (put_edge / take_edge); iterate 0's neighbour edges
+// come from global memory (written by earlier launches).  There is no grid
+// barrier: a workgroup waits only for its two neighbours' edges, and for the
+// tagged partial sums it needs for the stopping decision.  An edge slot is
+// written again two iterations later, and the writer cannot get there before
+// the reader has taken the old value: the writer's next iteration needs the
+// reader's edges, which the reader only publishes after that read.  A
+// partial-sum slot (kPartSlots of them, by iteration) is written again
+// kPartSlots iterations later, after its writer has taken a decision that
+// needs every workgroup's partial of an iteration whose end follows that
+// workgroup's last read of the slot.  No store has to complete before
+// another is issued.  At the end the final Psi and phi are written to global
+// memory.  T = float: refined path; T = double: plain FP64 path.  NP: padded
+// cell size; BS: threads per workgroup.
+template <typename T, int NP, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
 void k_oci_local(Slab S, StepIO io, int ntiles) {
     constexpr bool REF = sizeof(T) == 4;
@@ -633,169 +632,98 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     constexpr int CPT = BS / TPC;
     constexpr int V = 16 / sizeof(T);
     constexpr int NV = NP / V;
-    constexpr bool CACHE = RES && REF;
-    // Register-resident rows: one tile per workgroup (launched with nwg =
-    // ntiles), a cell's rows in one wave, and three LDS copies of Psi and phi
-    // (the iterate, the one being formed, and the one before).  Each wave
-    // then runs its cell's iteration on its own, with one workgroup barrier
-    // per iteration; the stopping decision lags one more iteration (its
-    // partial sums have long arrived when it is taken) and takes effect at
-    // that barrier.
-    constexpr bool DB = RES;
-    static_assert(!DB || TPC <= 64, "resident rows: one cell per wave or less");
-    static_assert(BS <= 1024, "wave sums are added within one row of 16 lanes");
-    constexpr int LAG = DB ? kResidentLag : 1;   // iteration l decides on e_(l - LAG + 1)
-    constexpr int NCOPY = DB ? kResidentCopies : 1;   // LDS copies of Psi and phi
     constexpr int PV = 4;               // partial sums per lane loaded ahead of the decision
     constexpr bool WAVE_CELL = TPC <= 64;   // a cell's rows lie in one wave (then RPT = 1)
+    static_assert(BS <= 1024, "wave sums are added within one row of 16 lanes");
     typedef typename Vec16<T>::type VT;
 
     extern __shared__ __align__(16) double s_dyn[];
     __shared__ __align__(16) T s_vec[CPT][NP];
     __shared__ double s_wx[CPT][NP];
-    __shared__ double s_coef[CACHE ? CPT : 1][CACHE ? NP : 1][4];
-    __shared__ double s_crow[CACHE ? CPT : 1][CACHE ? NP : 1];
-    __shared__ double s_scat[CACHE ? CPT : 1][CACHE ? NP / 8 * NP / 8 : 1];
     __shared__ double s_mu[NP / 4], s_w[NP / 4];
-    __shared__ double s_tmp[BS / 64 + 1];
     __shared__ double s_max[BS / 64];
     __shared__ double s_part[2][BS / 64];   // per-wave partial sums, by iteration parity
     __shared__ double s_dec[2][4];          // decision (done, status, e, rho), by iteration parity
-    __shared__ double s_psum[2][BS / 64];   // per-wave sums of the tagged partials, by iteration parity
-    __shared__ double s_eprev[2];           // e of the last decision, by iteration parity (kept out of registers)
 
     const int tid = threadIdx.x;
     const int dec_wave = (BS / 64) / 2;   // the wave that takes the stopping decision
     const int J = S.J, N = S.N, G = S.G, n = S.n, nh = S.N / 2, NG = S.N * S.G;
     const unsigned nwg = gridDim.x;
     const int wg = blockIdx.x;
-    const int tile0 = RES ? wg : (int)(((long)ntiles * wg) / nwg);
-    const int tile1 = RES ? wg + 1 : (int)(((long)ntiles * (wg + 1)) / nwg);
+    const int tile0 = (int)(((long)ntiles * wg) / nwg);
+    const int tile1 = (int)(((long)ntiles * (wg + 1)) / nwg);
     const int ntw = tile1 - tile0;
     const int c0 = tile0 * CPT;
     const int c1 = min(tile1 * CPT, J);
     const int ncell = ntw * CPT;
-    double *L_psi0 = s_dyn;                                        // [NCOPY][ncell][n]
-    double *L_phi0 = L_psi0 + (size_t)NCOPY * ncell * n;           // [NCOPY][ncell][4G]
-    double *L_snap = L_phi0 + (size_t)NCOPY * ncell * 4 * G;       // [ntw][2][NG]: R-going, L-going
+    double *L_psi = s_dyn;                                   // [ncell][n]
+    double *L_phi = L_psi + (size_t)ncell * n;               // [ncell][4G]
+    double *L_snap = L_phi + (size_t)ncell * 4 * G;          // [ntw][2][NG]: R-going, L-going
     // exchange buffer [2 parity][nwg][2 side][2 lev][G][nh] slots of two
     // words; side 0: my first cell's L corners of mu<0 angles, side 1: my
     // last cell's R corners of mu>0
-    const size_t exw = (size_t)2 * 2 * G * nh;   // edge slots per (parity, workgroup)
     uint64_t *exch_bits = reinterpret_cast<uint64_t *>(S.exch);
     auto exq = [&](int par, int w, int side, int lev, int g, int mm) -> uint64_t * {
-        return exch_bits + 2 * ((((size_t)par * nwg + w) * 2 + side) * (exw / 2) + ((size_t)lev * G + g) * nh + mm);
+        return exch_bits + 2 * ((((size_t)par * nwg + w) * 2 + side) * NG + ((size_t)lev * G + g) * nh + mm);
     };
 
     for (int m = tid; m < N; m += BS) { s_mu[m] = S.mu[m]; s_w[m] = S.w[m]; }
 
     const T *Xall = reinterpret_cast<const T *>(S.X);
-    VT xr[RES ? NV : 1];
-    if constexpr (RES) {
-        const int j = tile0 * CPT + tid / TPC;
-        if (j < J) {
-            const T *Xc = Xall + (size_t)j * NP * NP;
-#pragma unroll
-            for (int kv = 0; kv < NV; ++kv)
-                xr[kv] = *reinterpret_cast<const VT *>(Xc + ((size_t)kv * NP + tid % TPC) * V);
-        }
-    }
     // the iterate and its scalar flux into LDS
     const int base = S.ctl->base;
+    const double *__restrict__ psi_g = S.psi[base];   // the iterate in global memory: only read at l = 0
     {
-        const double *pin = S.psi[base] + (size_t)c0 * n;
+        const double *pin = psi_g + (size_t)c0 * n;
         const int tot = (c1 - c0) * n;
-        for (int k = tid; k < tot; k += BS) L_psi0[k] = pin[k];
+        for (int k = tid; k < tot; k += BS) L_psi[k] = pin[k];
         const double *fin = S.phi[base] + (size_t)c0 * 4 * G;
         const int totf = (c1 - c0) * 4 * G;
-        for (int k = tid; k < totf; k += BS) L_phi0[k] = fin[k];
+        for (int k = tid; k < totf; k += BS) L_phi[k] = fin[k];
     }
     __syncthreads();
-    if constexpr (CACHE) {
-        const int cl = tid / TPC, i = tid % TPC;
-        const int j = tile0 * CPT + cl;
-        if (j < J && i < n) {
-            const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
-            lc_row(S, j, g, s_mu[m], u, s_coef[cl][i]);
-            s_crow[cl][i] = S.crhs[(size_t)j * n + i];
-        }
-        if (j < J && i < G * G) s_scat[cl][i] = 0.25 * S.dx[j] * S.sigma_s[(size_t)j * G * G + i];
-        __syncthreads();
-    }
 
     const bool tree_phi = WAVE_CELL && (N & (N - 1)) == 0;
     uint64_t *part_bits = reinterpret_cast<uint64_t *>(S.partials);
-    const double *__restrict__ psi_g = S.psi[base];   // the iterate in global memory: only read at l = 0
     double e_prev = __builtin_nan("");
     uint64_t pv[PV];   // the decision wave's partial sums, loaded at the end of the previous iteration
 #pragma unroll
     for (int r = 0; r < PV; ++r) pv[r] = kSlotEmpty;
-    // Iteration l forms Psi^(l+1).  With one copy of Psi, one wave decides at
-    // its start, while the others wait for the neighbours' edges, on e_l (the
-    // partials of iteration l - 1); the outcome reaches every wave through
-    // the barrier that precedes the solve, before anything in LDS is
-    // overwritten.  With three copies the decision is on e_(l-1): every wave
-    // loads its share of the partials of iteration l - 2 at the start, sums
-    // it at the end, and after the barrier that ends the iteration every
-    // thread adds the shares in the same order and applies the rule.  Either
-    // way LDS still holds the final iterate when the decision stops the step.
+    // Iteration l forms Psi^(l+1).  At its start one wave decides, while the
+    // others wait for the neighbours' edges, on e_l (the partials of
+    // iteration l - 1); the outcome reaches every wave through the barrier
+    // that precedes the solve, before anything in LDS is overwritten, so LDS
+    // still holds the final iterate Psi^(l) when the decision stops the step.
     for (int l = 0;; ++l) {
         // lane indices are re-derived every iteration from an opaque copy, so
         // the compiler does not keep per-lane addresses live across the loop
-        // (registers are scarce next to the resident inverse rows)
         int tid_o = tid;
         asm volatile("" : "+v"(tid_o));
         const int cl = tid_o / TPC;
         const int t = tid_o % TPC;
-        const int cb = l % NCOPY;                        // LDS copy holding Psi^(l)
-        const int nb = (l + 1) % NCOPY;                  // ... Psi^(l+1)
-        double *L_psi = L_psi0 + (size_t)cb * ncell * n;
-        double *L_phi = L_phi0 + (size_t)cb * ncell * 4 * G;
-        double *N_psi = L_psi0 + (size_t)nb * ncell * n;
-        double *N_phi = L_phi0 + (size_t)nb * ncell * 4 * G;
-        const int lp = l - LAG;                          // iteration whose partials are decided on
+        const int lp = l - 1;                            // iteration whose partials are decided on
         const uint64_t *part_prev = part_bits + (size_t)(lp & (kPartSlots - 1)) * nwg;
         const int par = (l + 1) & 1;                     // exchange parity this iteration publishes
-        const bool dec = !DB && (tid_o >> 6) == dec_wave && lp >= 0;   // this wave decides (wave-uniform)
+        const bool dec = (tid_o >> 6) == dec_wave && lp >= 0;   // this wave decides (wave-uniform)
         double dsq_acc = 0.0;
         int bad = 0;
-        // resident rows: this wave's share of the partials of iteration lp,
-        // slots [s Sw, (s + 1) Sw) for share s, one per lane (more past 64
-        // lanes); the first and the last wave (the range's end cells, on the
-        // critical path) hold no share when there are four waves or more
-        constexpr int W = BS / 64;
-        constexpr int WS0 = W >= 4 ? 1 : 0;       // wave of share 0
-        constexpr int WSN = W >= 4 ? W - 2 : W;   // waves holding a share
-        const int Sw = ((int)nwg + WSN - 1) / WSN;
-        auto qslot = [&](int tq, bool *on) -> int {   // (re-derived where needed, to spare registers)
-            const int sh = (tq >> 6) - WS0;
-            const int q = sh * Sw + (tq & 63);
-            *on = DB && lp >= 0 && sh >= 0 && sh < WSN && (tq & 63) < Sw && q < (int)nwg;
-            return q;
-        };
-        uint64_t qv = kSlotEmpty;
-        {
-            bool on;
-            const int q = qslot(tid_o, &on);
-            if (on) qv = ld_bits(part_prev + q);
-        }
 
         // Stopping rule (section 2.1) on e_(lp+1), the change made by
         // iteration lp, in the decision wave: every workgroup's decision wave
         // sums the same tagged partials in the same order (lane k holds k,
         // k + 64, ...) and takes the same decision, left in s_dec.
-        auto wait_part = [&](uint64_t x, int k) -> double {
-            long spins = 0;
-#pragma clang loop unroll(disable)
-            while (!part_ready(x, lp)) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > kSpinLimit) { bad = 1; break; }
-                x = ld_bits(part_prev + k);
-            }
-            return part_value(x);
-        };
-        auto decide_wave = [&]() {
+        if (dec) {
             const int lane = tid_o & 63;
+            auto wait_part = [&](uint64_t x, int k) -> double {
+                long spins = 0;
+#pragma clang loop unroll(disable)
+                while (!part_ready(x, lp)) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > kSpinLimit) { bad = 1; break; }
+                    x = ld_bits(part_prev + k);
+                }
+                return part_value(x);
+            };
             double v = 0.0;
 #pragma unroll
             for (int r = 0; r < PV; ++r)
@@ -821,34 +749,10 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                 s_dec[l & 1][2] = e;
                 s_dec[l & 1][3] = rho;
             }
-        };
-        // After a stop: the final iterate Psi^(iters) and its flux leave LDS.
-        auto finish = [&](int iters, double e, double rho, int status) {
-            const int fin = (base + iters) & 1;
-            const int db = iters % NCOPY;
-            const double *D_psi = L_psi0 + (size_t)db * ncell * n;
-            const double *D_phi = L_phi0 + (size_t)db * ncell * 4 * G;
-            double *pout = S.psi[fin] + (size_t)c0 * n;
-            const int totp = (c1 - c0) * n;
-            for (int k = tid_o; k < totp; k += BS) pout[k] = D_psi[k];
-            double *fout = S.phi[fin] + (size_t)c0 * 4 * G;
-            const int totf = (c1 - c0) * 4 * G;
-            for (int k = tid_o; k < totf; k += BS) fout[k] = D_phi[k];
-            if (wg == 0 && tid_o == 0) {
-                Ctl *c = S.ctl;
-                c->iter = iters;
-                c->e_last = e;
-                c->rho = rho;
-                c->e_prev = e;
-                c->status = status;
-                c->done = 1;
-            }
-        };
-
-        if (dec) decide_wave();
+        }
 
         // edges crossing internal tile boundaries, before any tile updates
-        if (!DB && ntw > 1) {
+        if (ntw > 1) {
             for (int k = tid_o; k < (ntw - 1) * 2 * NG; k += BS) {
                 const int tt = 1 + k / (2 * NG), r = k % (2 * NG);
                 const int side = r / NG, q = r % NG;           // side 0: R-going, 1: L-going
@@ -866,12 +770,11 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             const int tt = tile - tile0;
             const int j = tile * CPT + cl;
             const bool live = j < J;
-            const double *Lp = L_psi + (size_t)(j - c0) * n;    // this cell's iterate
-            const double *Lf = L_phi + (size_t)(j - c0) * 4 * G;
-            double *Np = N_psi + (size_t)(j - c0) * n;          // ... and where the next one goes
-            double *Nf = N_phi + (size_t)(j - c0) * 4 * G;
+            double *Lp = L_psi + (size_t)(j - c0) * n;          // this cell's iterate
+            double *Lf = L_phi + (size_t)(j - c0) * 4 * G;
             double xold[RPT], bb[RPT];
             int expo = 0;
+
             // (1) b = constant part + lagged incident edge
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -882,7 +785,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                     const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
                     const double mu = s_mu[m];
                     xold[r] = Lp[i];
-                    b = CACHE ? s_crow[cl][i] : S.crhs[(size_t)j * n + i];
+                    b = S.crhs[(size_t)j * n + i];
                     const int lev = u >> 1;
                     if (mu > 0.0 && !(u & 1)) {
                         double e;
@@ -917,8 +820,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             }
             if (bad) __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if constexpr (REF) {
-                // (2) FP64 residual r = b - A_j Psi^(l), matrix-free, scaled
-                // by the power of two of its largest entry in the cell
+                // (2) FP64 residual r = b - A_j Psi^(l), matrix-free
                 double rr[RPT];
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
@@ -927,23 +829,14 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                     if (live && i < n) {
                         const int g = i / (4 * N), u = i & 3;
                         double cf[4];
-                        if constexpr (CACHE) {
-                            cf[0] = s_coef[cl][i][0]; cf[1] = s_coef[cl][i][1];
-                            cf[2] = s_coef[cl][i][2]; cf[3] = s_coef[cl][i][3];
-                        } else {
-                            lc_row(S, j, g, s_mu[(i >> 2) % N], u, cf);
-                        }
+                        lc_row(S, j, g, s_mu[(i >> 2) % N], u, cf);
                         const double *p = Lp + (i & ~3);
-                        const double lp = cf[0] * p[0] + cf[1] * p[1] + cf[2] * p[2] + cf[3] * p[3];
+                        const double lp4 = cf[0] * p[0] + cf[1] * p[1] + cf[2] * p[2] + cf[3] * p[3];
                         double sc = 0.0;
-                        if constexpr (CACHE) {
-                            for (int gp = 0; gp < G; ++gp) sc += s_scat[cl][g * G + gp] * Lf[gp * 4 + u];
-                        } else {
-                            const double *ss = S.sigma_s + ((size_t)j * G + g) * G;
-                            for (int gp = 0; gp < G; ++gp) sc += ss[gp] * Lf[gp * 4 + u];
-                            sc *= 0.25 * S.dx[j];
-                        }
-                        res = bb[r] - lp + sc;
+                        const double *ss = S.sigma_s + ((size_t)j * G + g) * G;
+                        for (int gp = 0; gp < G; ++gp) sc += ss[gp] * Lf[gp * 4 + u];
+                        sc *= 0.25 * S.dx[j];
+                        res = bb[r] - lp4 + sc;
                     }
                     rr[r] = res;
                 }
@@ -967,40 +860,43 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) s_vec[cl][t + r * TPC] = (T)ldexp(rr[r], -expo);
             }
-            if constexpr (DB) {
-                wave_sync();   // the cell's s_vec is complete (the cell is this wave's)
-            } else {
-                __syncthreads();   // s_vec and the decision complete; every read of this tile's Psi^(l) is done
-                if (tile == tile0 && lp >= 0 && s_dec[l & 1][0] != 0.0) {
-                    finish(lp + 1, s_dec[l & 1][2], s_dec[l & 1][3], (int)s_dec[l & 1][1]);
-                    return;
+            __syncthreads();   // s_vec and the decision complete; every read of this tile's Psi^(l) is done
+            if (tile == tile0 && lp >= 0 && s_dec[l & 1][0] != 0.0) {
+                // the final iterate Psi^(l) and its flux leave LDS
+                const int iters = lp + 1;
+                const int fin = (base + iters) & 1;
+                double *pout = S.psi[fin] + (size_t)c0 * n;
+                const int totp = (c1 - c0) * n;
+                for (int k = tid_o; k < totp; k += BS) pout[k] = L_psi[k];
+                double *fout = S.phi[fin] + (size_t)c0 * 4 * G;
+                const int totf = (c1 - c0) * 4 * G;
+                for (int k = tid_o; k < totf; k += BS) fout[k] = L_phi[k];
+                if (wg == 0 && tid_o == 0) {
+                    Ctl *c = S.ctl;
+                    c->iter = iters;
+                    c->e_last = s_dec[l & 1][2];
+                    c->rho = s_dec[l & 1][3];
+                    c->e_prev = s_dec[l & 1][2];
+                    c->status = (int)s_dec[l & 1][1];
+                    c->done = 1;
                 }
+                return;
             }
 
-            // (3) apply the inverse, one row per thread
+            // (3) apply the inverse, one row per thread, factors streamed as
+            // coalesced 16-byte words
             T acc[RPT];
 #pragma unroll
             for (int r = 0; r < RPT; ++r) acc[r] = T(0);
             if (live) {
-                if constexpr (RES) {
-                    // four partial sums, so the FMA chain is a quarter as long
-                    T a4[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-                    for (int kv = 0; kv < NV; ++kv) {
-                        const VT bv = *reinterpret_cast<const VT *>(&s_vec[cl][kv * V]);
-                        a4[kv & 3] += dot16(xr[kv], bv);
-                    }
-                    acc[0] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-                } else {
-                    const T *Xc = Xall + (size_t)j * NP * NP;
+                const T *Xc = Xall + (size_t)j * NP * NP;
 #pragma unroll 8
-                    for (int kv = 0; kv < NV; ++kv) {
-                        const VT bv = *reinterpret_cast<const VT *>(&s_vec[cl][kv * V]);
+                for (int kv = 0; kv < NV; ++kv) {
+                    const VT bv = *reinterpret_cast<const VT *>(&s_vec[cl][kv * V]);
 #pragma unroll
-                        for (int r = 0; r < RPT; ++r) {
-                            const VT xv = *reinterpret_cast<const VT *>(Xc + ((size_t)kv * NP + t + r * TPC) * V);
-                            acc[r] += dot16(xv, bv);
-                        }
+                    for (int r = 0; r < RPT; ++r) {
+                        const VT xv = *reinterpret_cast<const VT *>(Xc + ((size_t)kv * NP + t + r * TPC) * V);
+                        acc[r] += dot16(xv, bv);
                     }
                 }
             }
@@ -1014,7 +910,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                 const int i = t + r * TPC;
                 double x = REF ? xold[r] + ldexp((double)acc[r], expo) : (double)acc[r];
                 if (live && i < n) {
-                    Np[i] = x;
+                    Lp[i] = x;
                     if (S.norm == 1) dsq += (x - xold[r]) * (x - xold[r]);
                     const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
                     if (j == c0 && wg > 0 && m < nh && !(u & 1))
@@ -1041,7 +937,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                 if (live && t < n && (t >> 2) % N == 0) {
                     const int fi = (t / (4 * N)) * 4 + (t & 3);
                     const double f0 = Lf[fi];
-                    Nf[fi] = wx;
+                    Lf[fi] = wx;
                     if (S.norm == 0) dsq += (wx - f0) * (wx - f0);
                 }
             } else {
@@ -1050,14 +946,13 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                     const int i = t + r * TPC;
                     s_wx[cl][i] = (i < n ? s_w[(i >> 2) % N] : 0.0) * xs[r];
                 }
-                if constexpr (DB) wave_sync();
-                else __syncthreads();
+                __syncthreads();
                 if (live && t < 4 * G) {
                     const int g = t >> 2, u = t & 3;
                     double f = 0.0;
                     for (int m = 0; m < N; ++m) f += s_wx[cl][(g * N + m) * 4 + u];
                     const double f0 = Lf[t];
-                    Nf[t] = f;
+                    Lf[t] = f;
                     if (S.norm == 0) dsq += (f - f0) * (f - f0);
                 }
             }
@@ -1071,75 +966,20 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             const double v = wave_sum_dpp(dsq_acc);
             if ((tid_o & 63) == 0) s_part[l & 1][tid_o >> 6] = v;
         }
-        if (DB && lp >= 0) {
-            // this wave's share of the partials of iteration lp
-            double v = 0.0;
-            int tq = tid;
-            asm volatile("" : "+v"(tq));
-            bool on;
-            const int q0 = qslot(tq, &on);
-            if (on) {
-                const int b0 = q0 - (tq & 63);   // first slot of this wave's share
-                v = wait_part(qv, q0);
-                for (int k = (tq & 63) + 64; k < Sw && b0 + k < (int)nwg; k += 64)
-                    v += wait_part(ld_bits(part_prev + b0 + k), b0 + k);
-            }
-            if (bad) {
-                __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                v = __builtin_nan("");
-            }
-            v = wave_sum_dpp(v);
-            if ((tid_o & 63) == 0) s_psum[l & 1][tid_o >> 6] = v;
-        }
         __syncthreads();
-        if (DB) {
-            // the decision wave took the decision on the partials of
-            // iteration l - 1 - LAG after the previous barrier; it applies
-            // now, when every wave sees it (on a stop that iterate,
-            // Psi^(l-LAG), is intact in its LDS copy)
-            if (l - 1 - LAG >= 0 && s_dec[(l + 1) & 1][0] != 0.0) {
-                finish(l - LAG, s_dec[(l + 1) & 1][2], s_dec[(l + 1) & 1][3], (int)s_dec[(l + 1) & 1][1]);
-                return;
-            }
-            if (lp >= 0 && (tid_o >> 6) == dec_wave) {
-                // the stopping rule (section 2.1) on e_(lp+1) from the shares
-                // every wave left before the barrier, in the decision wave
-                // only (every workgroup's decision wave adds the same values in
-                // the same order)
-                double tot = 0.0;
-#pragma unroll
-                for (int w = 0; w < W; ++w) tot += s_psum[l & 1][w];
-                const int iters = lp + 1;
-                const double e = sqrt(tot);
-                const double rho = iters >= 2 ? e / s_eprev[(l + 1) & 1] : __builtin_nan("");
-                int done = 0, status = OK;
-                if (!isfinite(e)) { done = 1; status = NONFINITE; }
-                else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
-                else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - rho))) done = 1;
-                else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
-                if ((tid_o & 63) == 0) {
-                    s_eprev[l & 1] = e;
-                    s_dec[l & 1][0] = done;
-                    s_dec[l & 1][1] = status;
-                    s_dec[l & 1][2] = e;
-                    s_dec[l & 1][3] = rho;
-                }
-            }
-        }
         if (tid_o < 64) {
-            // wave 0 adds the W wave sums (lanes 0 .. W-1, a DPP row sum)
-            double s = (tid_o < W) ? s_part[l & 1][tid_o] : 0.0;
+            // wave 0 adds the wave sums (lanes 0 .. BS/64 - 1, a DPP row sum)
+            double s = (tid_o < BS / 64) ? s_part[l & 1][tid_o] : 0.0;
             s += dpp_f64<kDppXor1>(s);
             s += dpp_f64<kDppXor2>(s);
             s += dpp_f64<kDppHalfMirror>(s);
             s += dpp_f64<kDppMirror>(s);
             if (tid_o == 0) st_bits(part_bits + (size_t)(l & (kPartSlots - 1)) * nwg + wg, part_encode(s, l));
         }
-        // one copy: the decision wave loads the partials it decides on next time
+        // the decision wave loads the partials it decides on next time
         {
-            const int lq = l + 1 - LAG;
-            const bool dq = !DB && (tid_o >> 6) == dec_wave && lq >= 0;
-            const uint64_t *pq = part_bits + (size_t)(lq & (kPartSlots - 1)) * nwg;
+            const bool dq = (tid_o >> 6) == dec_wave;
+            const uint64_t *pq = part_bits + (size_t)(l & (kPartSlots - 1)) * nwg;
 #pragma unroll
             for (int r = 0; r < PV; ++r) {
                 const int k = (tid_o & 63) + 64 * r;
@@ -1830,7 +1670,7 @@ static hipError_t dispatch(bool fp32, int np, bool res, int bs, F f) {
 template <typename T, int NP, bool RES, int BS>
 static const void *local_kernel() {
     if constexpr (RES) return (const void *)&k_oci_res<T, NP, BS>;
-    else return (const void *)&k_oci_local<T, NP, false, BS>;
+    else return (const void *)&k_oci_local<T, NP, BS>;
 }
 
 template <typename T, int NP, bool RES, int BS>
