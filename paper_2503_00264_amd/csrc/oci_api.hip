@@ -16,6 +16,7 @@
 namespace oci {
 hipError_t launch_setup(const Slab &S, bool fp32, hipStream_t st);
 hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, hipStream_t st, int local_nwg);
+hipError_t launch_open(const Slab &S, const StepIO &io, hipStream_t st, int local_nwg);
 hipError_t launch_end(const Slab &S, const StepIO &io, hipStream_t st);
 hipError_t launch_oci_step(const Slab &S, const StepIO &io, bool fp32, int np, bool res, int bs, int nwg, int ntiles,
                            hipStream_t st, bool cooperative);
@@ -415,7 +416,8 @@ extern "C" int oci_step(oci_handle *h, const double *q_dev, const double *inc_le
     int rc = check_step_args(h, phi_out_dev, info_dev);
     if (rc) return rc;
     StepIO io{q_dev, inc_left_dev, inc_right_dev, phi_out_dev, psi_out_dev, info_dev};
-    HIPCHECK(launch_begin(h->S, io, h->need_broadcast, h->st, h->local ? h->nwg : 0));
+    if (h->need_broadcast || !h->local) HIPCHECK(launch_begin(h->S, io, h->need_broadcast, h->st, h->local ? h->nwg : 0));
+    else HIPCHECK(launch_open(h->S, io, h->st, h->nwg));
     h->need_broadcast = false;
     hipEvent_t e0 = h->profiling ? prof_event(h) : nullptr, e1 = h->profiling ? prof_event(h) : nullptr;
     if (e0) HIPCHECK(hipEventRecord(e0, h->st));

@@ -95,8 +95,7 @@ __device__ inline void begin_one(const Slab &S) {
 __global__ void k_begin_step(Slab S) { begin_one(S); }
 
 // phi of the first iterate: one thread per (j, g, u), m summed in order.
-__device__ inline void phi0_elem(const Slab &S, size_t t) {
-    const int b = S.ctl->base;
+__device__ inline void phi0_at(const Slab &S, size_t t, int b) {
     const int u = t & 3;
     const size_t jg = t >> 2;
     const double *p = S.psi[b] + jg * S.N * 4 + u;
@@ -104,6 +103,7 @@ __device__ inline void phi0_elem(const Slab &S, size_t t) {
     for (int m = 0; m < S.N; ++m) s += S.w[m] * p[m * 4];
     S.phi[b][t] = s;
 }
+__device__ inline void phi0_elem(const Slab &S, size_t t) { phi0_at(S, t, S.ctl->base); }
 // Also empties the hand-off slots of a workgroup-local launch of nwg
 // workgroups that follows (nwg = 0: none).
 __global__ __launch_bounds__(kBlock) void k_phi0(Slab S, int nwg) {
@@ -111,6 +111,25 @@ __global__ __launch_bounds__(kBlock) void k_phi0(Slab S, int nwg) {
     if (t < (size_t)S.J * S.G * 4) phi0_elem(S, t);
     const size_t nex = (size_t)8 * nwg * S.N * S.G;
     if (t < nex) reinterpret_cast<uint64_t *>(S.exch)[t] = kSlotEmpty;
+    if (t < (size_t)kPartSlots * nwg) reinterpret_cast<uint64_t *>(S.partials)[t] = kSlotEmpty;
+}
+
+__device__ inline void const_rhs_elem(const Slab &S, const StepIO &io, size_t t);
+
+// Opens a time step of a workgroup-local kernel in one launch when no state
+// broadcast is needed: the constant part of b, phi of the first iterate (the
+// last iterate of the previous step, in buffer (base + iter) & 1) and the
+// empty hand-off slots of a launch of nwg workgroups.  The control block is
+// left as the previous step left it: the local kernels take the first
+// iterate's buffer from it the same way and rewrite it when they stop, and
+// k_end_step clears its error flag once reported.
+__global__ __launch_bounds__(kBlock) void k_step_open(Slab S, StepIO io, int nwg) {
+    const Ctl *c = S.ctl;
+    const int nb = (c->base + c->iter) & 1;
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < (size_t)S.J * S.n) const_rhs_elem(S, io, t);
+    if (t < (size_t)S.J * S.G * 4) phi0_at(S, t, nb);
+    if (t < (size_t)8 * nwg * S.N * S.G) reinterpret_cast<uint64_t *>(S.exch)[t] = kSlotEmpty;
     if (t < (size_t)kPartSlots * nwg) reinterpret_cast<uint64_t *>(S.partials)[t] = kSlotEmpty;
 }
 
@@ -148,6 +167,7 @@ __device__ inline void end_elem(const Slab &S, const StepIO &io, size_t t) {
         ip[1] = c->err ? -6 : c->status;
         dp[1] = c->e_last;
         dp[2] = c->rho;
+        const_cast<Ctl *>(c)->err = 0;   // reported; the next step starts clean
     }
 }
 __device__ inline size_t end_elems(const Slab &S) {
@@ -168,6 +188,13 @@ __device__ inline float dot16(const float4 &a, const float4 &b) {
     return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
 }
 __device__ inline double dot16(const double2 &a, const double2 &b) { return a.x * b.x + a.y * b.y; }
+// acc + a . b as a chain of fused multiply-adds
+__device__ inline float fma_dot16(const float4 &a, const float4 &b, float acc) {
+    return fmaf(a.w, b.w, fmaf(a.z, b.z, fmaf(a.y, b.y, fmaf(a.x, b.x, acc))));
+}
+__device__ inline double fma_dot16(const double2 &a, const double2 &b, double acc) {
+    return fma(a.y, b.y, fma(a.x, b.x, acc));
+}
 
 template <int BS>
 __device__ inline double block_sum_t(double v, double *s_tmp) {
@@ -671,7 +698,9 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
 
     const T *Xall = reinterpret_cast<const T *>(S.X);
     // the iterate and its scalar flux into LDS
-    const int base = S.ctl->base;
+    // the first iterate is the last one of the previous step (a step opened
+    // by k_step_open leaves the control block as that step left it)
+    const int base = (S.ctl->base + S.ctl->iter) & 1;
     const double *__restrict__ psi_g = S.psi[base];   // the iterate in global memory: only read at l = 0
     {
         const double *pin = psi_g + (size_t)c0 * n;
@@ -873,6 +902,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                 for (int k = tid_o; k < totf; k += BS) fout[k] = L_phi[k];
                 if (wg == 0 && tid_o == 0) {
                     Ctl *c = S.ctl;
+                    c->base = base;
                     c->iter = iters;
                     c->e_last = s_dec[l & 1][2];
                     c->rho = s_dec[l & 1][3];
@@ -1111,7 +1141,9 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
         if constexpr (REF)
             if ((rinfo & res::CELL) && t < G * G) s_scat[cl][t] = 0.25 * S.dx[j] * S.sigma_s[(size_t)j * G * G + t];
     }
-    const int base = S.ctl->base;
+    // the first iterate is the last one of the previous step (a step opened
+    // by k_step_open leaves the control block as that step left it)
+    const int base = (S.ctl->base + S.ctl->iter) & 1;
     const double *__restrict__ psi_g = S.psi[base];   // the iterate in global memory: only read at l = 0
     {
         const double *pin = psi_g + (size_t)c0 * n;
@@ -1203,12 +1235,13 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
         }
         wave_sync();   // the cell's s_vec is complete (the cell is this wave's)
 
-        // (3) apply the inverse (four partial sums: a quarter of the FMA chain)
+        // (3) apply the inverse: four FMA chains over the row, a quarter as
+        // long as one
         T a4[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int kv = 0; kv < NV; ++kv) {
             const VT bv = *reinterpret_cast<const VT *>(&s_vec[cl][kv * V]);
-            a4[kv & 3] += dot16(xr[kv], bv);
+            a4[kv & 3] = fma_dot16(xr[kv], bv, a4[kv & 3]);
         }
         const T acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
 
@@ -1256,7 +1289,18 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
         // (5) this wave's sum of squared changes and its share of the
         // partials of iteration lp, then the barrier
         {
-            const double v = wave_sum_dpp(dsq);
+            double v;
+            if (S.norm == 0 && G == 1 && tree_phi) {
+                // the changes sit in lanes 0 .. 3 of each cell (m = 0, g = 0)
+                double q = dsq;
+                q += dpp_f64<kDppXor1>(q);
+                q += dpp_f64<kDppXor2>(q);
+                v = 0.0;
+#pragma unroll
+                for (int c = 0; c < 64 / TPC; ++c) v += readlane_f64(q, c * TPC);
+            } else {
+                v = wave_sum_dpp(dsq);
+            }
             if ((tid & 63) == 0) s_part[l & 1][tid >> 6] = v;
         }
         if (lp >= 0) {
@@ -1301,6 +1345,7 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
             for (int k = tid; k < totf; k += BS) fout[k] = D_phi[k];
             if (wg == 0 && tid == 0) {
                 Ctl *c = S.ctl;
+                c->base = base;
                 c->iter = iters;
                 c->e_last = s_dec[(l + 1) & 1][2];
                 c->rho = s_dec[(l + 1) & 1][3];
@@ -1673,20 +1718,40 @@ static const void *local_kernel() {
     else return (const void *)&k_oci_local<T, NP, BS>;
 }
 
+// Raises a kernel's dynamic LDS limit to all the LDS its static part leaves,
+// once per device.
+static hipError_t allow_dynamic_lds(const void *f, int *done) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (done[dev]) return hipSuccess;
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, f);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - a.sharedSizeBytes));
+    if (e == hipSuccess) done[dev] = 1;
+    return e;
+}
+
+// The persistent local kernels are launched as ordinary kernels: the grid
+// never exceeds what the occupancy query says fits at once, so on an
+// otherwise idle device every workgroup is resident; the bounded waits turn
+// a violation into OCI_ERR_DEVICE instead of a hang.
 template <typename T, int NP, bool RES, int BS>
 static hipError_t launch_local_t(const Slab &S, const StepIO &io, int nwg, int ntiles, size_t dyn, hipStream_t st) {
     if (RES && nwg != ntiles) return hipErrorInvalidValue;
+    static int attr_done[64] = {0};
     const void *f = local_kernel<T, NP, RES, BS>();
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    hipError_t e = allow_dynamic_lds(f, attr_done);
     if (e != hipSuccess) return e;
     void *args[] = {(void *)&S, (void *)&io, (void *)&ntiles};
-    return hipLaunchCooperativeKernel(f, dim3(nwg), dim3(BS), args, (unsigned)dyn, st);
+    return hipLaunchKernel(f, dim3(nwg), dim3(BS), args, dyn, st);
 }
 
 template <typename T, int NP, bool RES, int BS>
 static hipError_t occupancy_local_t(int *blocks, size_t dyn) {
+    static int attr_done[64] = {0};
     const void *f = local_kernel<T, NP, RES, BS>();
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    hipError_t e = allow_dynamic_lds(f, attr_done);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, BS, dyn);
 }
@@ -1765,6 +1830,14 @@ hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, h
     const size_t nex = (size_t)8 * local_nwg * S.N * S.G;
     if (nex > tot) tot = nex;
     hipLaunchKernelGGL(k_phi0, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S, local_nwg);
+    return hipGetLastError();
+}
+
+hipError_t launch_open(const Slab &S, const StepIO &io, hipStream_t st, int local_nwg) {
+    size_t tot = (size_t)S.J * S.n;
+    const size_t nex = (size_t)8 * local_nwg * S.N * S.G;
+    if (nex > tot) tot = nex;
+    hipLaunchKernelGGL(k_step_open, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S, io, local_nwg);
     return hipGetLastError();
 }
 
