@@ -38,6 +38,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X_HBM_GBS = 8000.0       # published HBM3E peak, GB/s
+MI355X_FP32_TFLOPS = 157.3    # published FP32 vector peak
+MI355X_FP64_TFLOPS = 78.6     # published FP64 vector peak
 
 
 def parse():
@@ -149,10 +151,18 @@ def recorded_traffic(label):
 
 def roofline_for(prim, probs, fp32):
     """Roofline of the dominant kernel (the persistent OCI kernel of the
-    measured path, one launch per time step).  Algorithmic bytes per
-    cell-iteration: the factor stream plus iterate, edge, source and flux
+    measured path, one launch per time step).
+
+    Streamed inverse rows: bound by memory; algorithmic bytes per
+    cell-iteration are the factor stream plus iterate, edge, source and flux
     traffic, 4 n^2 + 4 n + 128 N G + 64 G (FP32 factors) or
-    8 n^2 + 4 n + 96 N G + 64 G (FP64)."""
+    8 n^2 + 4 n + 96 N G + 64 G (FP64), against the HBM peak.
+
+    Register-resident rows (k_oci_res): the factor stream is gone (the rows
+    are loaded once per launch) and the kernel is bound by VALU issue; the
+    algorithmic work is the 2 n^2 flops per cell-iteration of the inverse
+    product, against the FP32 vector peak.  The stream model's figure is kept
+    beside it (`stream_model`)."""
     p = probs[0]
     N, G = p["N"], p["G"]
     n = 4 * N * G
@@ -163,22 +173,30 @@ def roofline_for(prim, probs, fp32):
     launches = sum(k[1] for k in prim["kernel"])
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
     bpc = (4 * n * n + 4 * n + 128 * N * G + 64 * G) if fp32 else (8 * n * n + 4 * n + 96 * N * G + 64 * G)
+    fpc = 2 * n * n
     cpl = prim["cell_solves"] / max(launches, 1)
-    achieved = bpc * cpl / avg_launch_s / 1e9
+    gbs = bpc * cpl / avg_launch_s / 1e9
+    tflops = fpc * cpl / avg_launch_s / 1e12
     label = kernel_label(prim["configs"][0], fp32, np_)
     tr = recorded_traffic(label)
-    resident = bool(prim["configs"][0].get("resident"))
-    note = ("inverse rows held in registers for the whole step: the algorithmic bytes count the "
-            "factor stream of every iteration, which this kernel does not re-read, so frac can "
-            "exceed 1; traffic is the HBM bytes actually moved" if resident else
-            "inverse rows streamed from memory every iteration")
-    return dict(bound="hbm", achieved=round(achieved, 1), peak=MI355X_HBM_GBS, unit="GB/s",
-                frac=round(achieved / MI355X_HBM_GBS, 4),
-                traffic=None if tr is None else round(tr * cpl, 1), note=note,
-                kernel=label, avg_launch_us=round(avg_launch_s * 1e6, 2),
-                cell_iterations_per_launch=round(cpl, 1), bytes_per_cell_iteration=bpc,
-                flops_per_cell_iteration=2 * n * n,
-                achieved_tflops=round(2 * n * n * cpl / avg_launch_s / 1e12, 3))
+    traffic = None if tr is None else round(tr * cpl, 1)
+    common = dict(kernel=label, avg_launch_us=round(avg_launch_s * 1e6, 2),
+                  cell_iterations_per_launch=round(cpl, 1), bytes_per_cell_iteration=bpc,
+                  flops_per_cell_iteration=fpc)
+    if prim["configs"][0].get("resident"):
+        peak = MI355X_FP32_TFLOPS if fp32 else MI355X_FP64_TFLOPS
+        return dict(bound="alu", achieved=round(tflops, 3), peak=peak, unit="TFLOP/s",
+                    frac=round(tflops / peak, 4), traffic=traffic,
+                    note="inverse rows held in VGPRs for the whole step; bound by VALU issue "
+                         "(the FP64 residual, reductions and address arithmetic beside the "
+                         "2 n^2-flop product); traffic = HBM bytes per launch from the PMC counters",
+                    stream_model=dict(achieved=round(gbs, 1), peak=MI355X_HBM_GBS, unit="GB/s",
+                                      frac=round(gbs / MI355X_HBM_GBS, 4)),
+                    **common)
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=MI355X_HBM_GBS, unit="GB/s",
+                frac=round(gbs / MI355X_HBM_GBS, 4), traffic=traffic,
+                note="inverse rows streamed from memory every iteration",
+                achieved_tflops=round(tflops, 3), **common)
 
 
 def cpu_baseline(prob, seconds):
