@@ -256,59 +256,150 @@ __device__ inline void copy16(void *dst, const void *src) {
     *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
 }
 
-// Workgroup choice of the pivot from each thread's candidate (magnitude
-// `best` < 0 when it has none, row `bi`, signed value `bv`): the largest
-// magnitude, the lowest row on ties.  Returns the row and sets *pa to the
-// signed pivot, or returns -1 when every candidate is zero.
+// Lane moves inside rows of 16 lanes (DPP, no LDS round trip) for the pivot
+// search; called with every lane of the wave active.
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <- 7 - i within 8
+constexpr int kDppMirror = 0x140;      // lane i <- 15 - i within 16
+template <int CTRL>
+__device__ inline unsigned dpp_u32(unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ inline unsigned lane_u32(unsigned v, int lane) {
+    return (unsigned)__builtin_amdgcn_readlane((int)v, lane);
+}
+// Maximum and minimum over the 64 lanes of the wave; every lane gets them.
+__device__ inline unsigned wave_max_u32(unsigned v) {
+    v = max(v, dpp_u32<kDppXor1>(v));
+    v = max(v, dpp_u32<kDppXor2>(v));
+    v = max(v, dpp_u32<kDppHalfMirror>(v));
+    v = max(v, dpp_u32<kDppMirror>(v));
+    return max(max(lane_u32(v, 0), lane_u32(v, 16)), max(lane_u32(v, 32), lane_u32(v, 48)));
+}
+__device__ inline unsigned wave_min_u32(unsigned v) {
+    v = min(v, dpp_u32<kDppXor1>(v));
+    v = min(v, dpp_u32<kDppXor2>(v));
+    v = min(v, dpp_u32<kDppHalfMirror>(v));
+    v = min(v, dpp_u32<kDppMirror>(v));
+    return min(min(lane_u32(v, 0), lane_u32(v, 16)), min(lane_u32(v, 32), lane_u32(v, 48)));
+}
+
+// Elements q .. q+V-1 of a register vector from / to one 16-byte word.
+template <typename R>
+__device__ inline void get16(R &v, int q, const float *s) {
+    const f32x4 w = *reinterpret_cast<const f32x4 *>(s);
+    v[q] = w.x;
+    v[q + 1] = w.y;
+    v[q + 2] = w.z;
+    v[q + 3] = w.w;
+}
+template <typename R>
+__device__ inline void get16(R &v, int q, const double *s) {
+    const double2 w = *reinterpret_cast<const double2 *>(s);
+    v[q] = w.x;
+    v[q + 1] = w.y;
+}
+template <typename R>
+__device__ inline void put16(float *d, const R &v, int q) {
+    *reinterpret_cast<f32x4 *>(d) = f32x4{v[q], v[q + 1], v[q + 2], v[q + 3]};
+}
+template <typename R>
+__device__ inline void put16(double *d, const R &v, int q) {
+    *reinterpret_cast<double2 *>(d) = double2{v[q], v[q + 1]};
+}
+
+// |v| as an unsigned key in two words (ordered like the magnitude).
+__device__ inline void mag_key(float v, unsigned &hi, unsigned &lo) {
+    hi = __float_as_uint(v) & 0x7fffffffu;
+    lo = 0;
+}
+__device__ inline void mag_key(double v, unsigned &hi, unsigned &lo) {
+    hi = (unsigned)__double2hiint(v) & 0x7fffffffu;
+    lo = (unsigned)__double2loint(v);
+}
+
+// The cell matrix (the same entries as cell_entry) written row by row into
+// its tiled np x np block X: one thread per row with the row's constants
+// computed once, and the cell's weights w_m and scattering coefficients
+// dx Sigma_s / 4 staged in LDS (`cw`, N + G^2 doubles).  Columns come in
+// blocks of the four unknowns of one (group, angle).
 template <typename T, int BS>
-__device__ int gj_pick(T best, int bi, T bv, T *s_wv, int *s_wi, T *pa) {
-    constexpr int W = BS / 64;
-    for (int off = 32; off > 0; off >>= 1) {
-        const T ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        const T ov = __shfl_xor(bv, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; bv = ov; }
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        s_wv[wave] = bv;
-        s_wi[wave] = best < T(0) ? -1 : bi;
-    }
+__device__ void assemble_tiled(const Slab &S, int j, T *X, double *cw) {
+    constexpr int V = 16 / (int)sizeof(T);
+    const int N = S.N, G = S.G, n = S.n, np = S.np;
+    const double dx = S.dx[j];
+    double *css = cw + N;
+    for (int i = threadIdx.x; i < N; i += BS) cw[i] = S.w[i];
+    for (int i = threadIdx.x; i < G * G; i += BS) css[i] = 0.25 * dx * S.sigma_s[(size_t)j * G * G + i];
     __syncthreads();
-    T b = T(-1), v = T(0);
-    int i0 = -1;
-    for (int w = 0; w < W; ++w) {
-        const int iw = s_wi[w];
-        if (iw < 0) continue;
-        const T m = fabs(s_wv[w]);
-        if (m > b || (m == b && iw < i0)) { b = m; i0 = iw; v = s_wv[w]; }
+    for (int r = threadIdx.x; r < np; r += BS) {
+        double Lr[4] = {0.0, 0.0, 0.0, 0.0};
+        int g = 0, m = 0, u = 0;
+        if (r < n) {
+            g = r / (4 * N);
+            m = (r >> 2) % N;
+            u = r & 3;
+            const double sig = S.sigma_t[(size_t)j * G + g];
+            const double a = dx / (S.speed[g] * S.dt);
+            const double mu = S.mu[m];
+            const double d = 0.5 * (fabs(mu) + dx * sig), h = 0.5 * mu;
+            // row u of L = [[d, h, a/2, 0], [-h, d, 0, a/2], [-a, 0, a+d, h], [0, -a, -h, a+d]]
+            if (u == 0) { Lr[0] = d; Lr[1] = h; Lr[2] = 0.5 * a; }
+            else if (u == 1) { Lr[0] = -h; Lr[1] = d; Lr[3] = 0.5 * a; }
+            else if (u == 2) { Lr[0] = -a; Lr[2] = a + d; Lr[3] = h; }
+            else { Lr[1] = -a; Lr[2] = -h; Lr[3] = a + d; }
+        }
+        const double *ssr = css + g * G;
+        int gc = 0, mc = 0;
+        for (int blk = 0; blk < np / 4; ++blk) {
+            T v[4];
+            if (r >= n || 4 * blk >= n) {  // padding: identity
+                for (int uc = 0; uc < 4; ++uc) v[uc] = 4 * blk + uc == r ? T(1) : T(0);
+            } else {
+                const double sc = ssr[gc] * cw[mc];
+                const bool diag = gc == g && mc == m;
+                for (int uc = 0; uc < 4; ++uc) {
+                    double x = uc == u ? -sc : 0.0;
+                    if (diag) x += Lr[uc];
+                    v[uc] = (T)x;
+                }
+            }
+            for (int w = 0; w < 4 / V; ++w) copy16(X + ((size_t)(blk * (4 / V) + w) * np + r) * V, v + w * V);
+            if (++mc == N) { mc = 0; ++gc; }
+        }
     }
-    *pa = v;
-    return b > T(0) ? i0 : -1;
 }
 
 // Assemble the cell matrix into the cell's tiled slot of the factor buffer
-// and replace it by its inverse (np >= 128, a multiple of NB and of 16).
+// and replace it by its inverse (np >= 128, a multiple of NB and of 16, and
+// np <= BS: thread r owns row r of the panel).
 //
-// Gauss-Jordan with row exchanges: eliminating column k with pivot row p
-// first swaps rows k and p, scales row k by 1/a_kk (storing 1/a_kk in place
-// of a_kk) and subtracts a_ik times row k from every other row i (storing
-// -a_ik/a_kk in place of a_ik).  After all n columns the matrix holds
-// A^-1 with its columns permuted: X[:, c] = T[:, sigma(c)], where sigma
-// applies the exchanges (k, p_k) to the column index in order k = 0, 1, ...
+// Gauss-Jordan: eliminating column k with pivot row p scales row p by 1/a_pk
+// (storing 1/a_pk in place of a_pk) and subtracts a_ik times that row from
+// every other row i (storing -a_ik/a_pk in place of a_ik).  Rows are moved as
+// the elimination goes so that the pivot of column k ends in row k; the
+// result T then holds A^-1 with its columns permuted: X[:, c] = T[:, sigma(c)]
+// where sigma(c) is the final position of the row that started as row c.
 //
-// Blocking: the NB columns [k0, k0+NB) are eliminated in LDS (panel P, all
-// n rows, exchanges applied there).  Their combined effect on any other
-// column x is x <- (x with its rows exchanged and rows k0..k0+NB-1 zeroed)
-// + P x_piv, where x_piv holds that column's entries in the NB pivot rows
-// before the panel; these rows are gathered into LDS (Bp) and the product
-// runs as 16x16x4 MFMAs, one wave per 16-column stripe.  A row outside the
-// pivot block whose content moved there by an exchange can only have come
-// from inside the block, and each stripe writes the block's own row tiles
-// last, so every read of a moved row precedes its overwrite in the same
-// wave.  In the MFMA the output tile is transposed (A operand = Bp, B operand
-// = P), which leaves each lane holding four consecutive columns of one row:
-// one 16-byte word of the tiled layout.  The contraction index is split as
+// Blocking: the NB columns [k0, k0+NB) are eliminated with each thread's
+// panel row in registers.  The pivot of each column is the largest magnitude
+// among the rows not yet used as pivots, the lowest row winning ties: a DPP
+// reduction per wave and one workgroup barrier per column, each wave
+// publishing its best row beside its key so the winner's row needs no second
+// round.  Then the pivot rows move to rows k0 .. k0+NB-1 and the rows they
+// displace from that block take the vacated places.  The panel's effect on
+// any other column x is x <- (x with those moves applied and rows
+// k0..k0+NB-1 zeroed) + P x_piv, where x_piv holds that column's entries in
+// the NB pivot rows before the panel.  The product runs as 16x16x4 MFMAs, one
+// wave per 16-column stripe, each wave reading the pivot rows' entries of its
+// stripe before it overwrites the stripe.  A row outside the block whose
+// content moved can only have come from inside the block, and each stripe
+// writes the block's row tiles last, so every read of a moved row precedes
+// its overwrite in the same wave.  In the MFMA the output tile is transposed
+// (A operand = pivot rows, B operand = P), which leaves each lane holding
+// four consecutive columns of one row: one 16-byte word of the tiled layout
+// for float, two for double.  The contraction index is split as
 // k = (lane / 16) * NB/4 + step, so each lane reads its P operands as
 // consecutive words.
 template <typename T, int NB, int BS>
@@ -316,122 +407,152 @@ __global__ __launch_bounds__(BS) void k_gj_invert(Slab S, int j0) {
     using Q = typename Quad<T>::type;
     constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte word
     constexpr int LDP = NB + V;             // panel row stride (elements)
-    constexpr int PADB = 16;                // Bp row padding (elements)
     constexpr int W = BS / 64;
     constexpr int KQ = NB / 4;              // MFMA steps per rank-NB update
     constexpr int SC = (kMaxN + BS - 1) / BS;
-    constexpr int U = 2;                    // row tiles per MFMA group
-    static_assert(NB % 16 == 0 && KQ % V == 0 && BS % 64 == 0, "shape");
+    constexpr int U = 2 * V;                // row tiles per MFMA group (loads in flight)
+    static_assert(NB % 16 == 0 && NB <= 64 && KQ % V == 0 && BS % 64 == 0, "shape");
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_src[kMaxN];
+    __shared__ int s_src[kMaxN];  // physical row -> its row at the start of the panel
+    __shared__ int s_np[kMaxN];   // row at the start of the panel -> physical row after it
     __shared__ int s_sig[kMaxN];
-    __shared__ T s_wv[W];
-    __shared__ int s_wi[W];
+    __shared__ int s_pl[NB];      // pivot row of each panel column
+    __shared__ int s_mark[NB];
+    __shared__ int s_out[NB];
+    __shared__ uint4 s_key[2][W];  // each wave's best candidate: magnitude words, row
+    __shared__ __align__(16) T s_wr[2][W][NB];
     const int j = j0 + blockIdx.x;
     if (j >= S.J) return;
     const int n = S.np, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ldb = n + PADB, nvb = n / V;
+    const int nvb = n / V;
+    const bool own = tid < n;
     T *P = reinterpret_cast<T *>(smem);  // [n][LDP]
-    T *Bp = P + (size_t)n * LDP;         // [NB][ldb]
     T *X = reinterpret_cast<T *>(S.X) + (size_t)j * n * n;
 
-    for (int e = tid; e < n * nvb; e += BS) {
-        const int r = e % n, cb = e / n;
-        T v[V];
-        for (int u = 0; u < V; ++u) v[u] = (T)cell_entry(S, j, r, cb * V + u);
-        copy16(X + ((size_t)cb * n + r) * V, v);
-    }
+    assemble_tiled<T, BS>(S, j, X, reinterpret_cast<double *>(smem));
     int sig[SC];
     for (int t = 0; t < SC; ++t) sig[t] = tid + t * BS;
+    if (tid < NB) s_mark[tid] = 0;
     __syncthreads();
 
     const int g = lane >> 4, li = lane & 15;
     const int nrt = n / 16, nstripe = (n - NB) / 16;
     for (int k0 = 0; k0 < n; k0 += NB) {
-        for (int e = tid; e < n * (NB / V); e += BS) {
-            const int r = e % n, q = e / n;
-            copy16(P + r * LDP + q * V, X + ((size_t)(k0 / V + q) * n + r) * V);
+        // this thread's panel row, a register vector indexed by the
+        // wave-uniform column (dynamic register indexing, no memory)
+        typedef T Row __attribute__((ext_vector_type(NB)));
+        Row pr{};
+        if (own)
+#pragma unroll
+            for (int q = 0; q < NB; q += V) get16(pr, q, X + ((size_t)((k0 + q) / V) * n + tid) * V);
+        for (int r = tid; r < n; r += BS) {
+            s_src[r] = r;
+            s_np[r] = r;
         }
-        for (int r = tid; r < n; r += BS) s_src[r] = r;
-        __syncthreads();
-        T pa;
-        int p;
-        {
-            T best = T(-1), bv = T(0);
-            int bi = n;
-            for (int r = k0 + tid; r < n; r += BS) {
-                const T v = P[r * LDP];
-                if (fabs(v) > best) { best = fabs(v); bi = r; bv = v; }
-            }
-            p = gj_pick<T, BS>(best, bi, bv, s_wv, s_wi, &pa);
-        }
+        bool cand = own && tid >= k0;
         for (int kk = 0; kk < NB; ++kk) {
-            const int k = k0 + kk;
-            if (p < 0) {
+            const int par = kk & 1;
+            unsigned mh = 0, ml = 0;
+            if (cand) mag_key(pr[kk], mh, ml);
+            const unsigned wh = wave_max_u32(mh);
+            if (mh != wh) ml = 0;
+            const unsigned wl = sizeof(T) == 8 ? wave_max_u32(ml) : 0u;
+            const unsigned mine = cand && mh == wh && ml == wl ? (unsigned)tid : ~0u;
+            const unsigned wr = wave_min_u32(mine);
+            if (lane == 0) s_key[par][wave] = uint4{wh, wl, wr, 0u};
+            if ((unsigned)tid == wr)
+#pragma unroll
+                for (int q = 0; q < NB; q += V) put16(&s_wr[par][wave][q], pr, q);
+            __syncthreads();
+            uint4 key[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) key[w] = s_key[par][w];
+            unsigned bh = 0, bl = 0, br = ~0u;
+            int bw = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const unsigned h = key[w].x, l = key[w].y, rw = key[w].z;
+                const bool better = rw != ~0u && (h > bh || (h == bh && (l > bl || (l == bl && rw < br))));
+                bh = better ? h : bh;
+                bl = better ? l : bl;
+                br = better ? rw : br;
+                bw = better ? w : bw;
+            }
+            if ((bh | bl) == 0) {  // every candidate is zero
                 if (tid == 0) atomicOr(&S.ctl->singular, 1);
                 return;
             }
-            const T inv = T(1) / pa;
-            if (tid < NB) {
-                const T vk = P[k * LDP + tid], vp = P[p * LDP + tid];
-                P[k * LDP + tid] = tid == kk ? inv : vp * inv;
-                if (p != k) P[p * LDP + tid] = vk;
-            }
-            if (tid == 0 && p != k) {
-                const int t = s_src[k];
-                s_src[k] = s_src[p];
-                s_src[p] = t;
-            }
-            for (int t = 0; t < SC; ++t) {
-                if (sig[t] == k) sig[t] = p;
-                else if (sig[t] == p) sig[t] = k;
-            }
-            __syncthreads();
-            T best = T(-1), bv = T(0);
-            int bi = n;
-            const T *prow = P + k * LDP;
-            for (int r = tid; r < n; r += BS) {
-                T *row = P + r * LDP;
-                if (r != k) {
-                    const T f = row[kk];
+            const int p = (int)br;
+            Row pn;
 #pragma unroll
-                    for (int c = 0; c < NB; c += V) {
-                        T a[V], b[V];
-                        copy16(a, row + c);
-                        copy16(b, prow + c);
-                        for (int u = 0; u < V; ++u) a[u] -= f * b[u];
-                        copy16(row + c, a);
-                    }
-                    row[kk] = -f * inv;
-                }
-                if (kk + 1 < NB && r > k) {
-                    const T v = row[kk + 1];
-                    if (fabs(v) > best) { best = fabs(v); bi = r; bv = v; }
-                }
+            for (int q = 0; q < NB; q += V) get16(pn, q, &s_wr[par][bw][q]);
+            const T inv = T(1) / pn[kk];
+            if (tid == p) {
+                pr = pn * inv;
+                pr[kk] = inv;
+                cand = false;
+            } else if (own) {
+                const T fi = pr[kk] * inv;
+                pr -= fi * pn;
+                pr[kk] = -fi;
             }
-            if (kk + 1 < NB) p = gj_pick<T, BS>(best, bi, bv, s_wv, s_wi, &pa);
-            else __syncthreads();
+            if (tid == 0) s_pl[kk] = p;
         }
 
-        // the panel is final: store it, and gather the pivot rows of the rest
+        // pivot rows to k0 .. k0+NB-1, displaced block rows to the vacated rows
+        __syncthreads();
+        const int stamp = k0 + 1;
+        int pk = -1;
+        if (tid < NB) {
+            pk = s_pl[tid];
+            if (pk < k0 + NB) s_mark[pk - k0] = stamp;
+        }
+        __syncthreads();
+        const bool outside = tid < NB && pk >= k0 + NB;
+        const bool unchosen = tid < NB && s_mark[tid] != stamp;
+        int rank_u = 0;
+        if (wave == 0) {
+            const unsigned long long below = (1ull << lane) - 1;
+            const unsigned long long bo = __ballot(outside), bu = __ballot(unchosen);
+            rank_u = __popcll(bu & below);
+            if (outside) s_out[__popcll(bo & below)] = pk;
+            if (tid < NB) {
+                s_src[k0 + tid] = pk;
+                s_np[pk] = k0 + tid;
+            }
+        }
+        __syncthreads();
+        if (unchosen) {
+            const int q = s_out[rank_u];
+            s_src[q] = k0 + tid;
+            s_np[k0 + tid] = q;
+        }
+        __syncthreads();
+        if (own) {
+            T *dst = P + s_np[tid] * LDP;
+#pragma unroll
+            for (int q = 0; q < NB; q += V) put16(dst + q, pr, q);
+        }
+        for (int t = 0; t < SC; ++t)
+            if (tid + t * BS < n) sig[t] = s_np[sig[t]];
+        __syncthreads();
+
+        // the panel is final
         for (int e = tid; e < n * (NB / V); e += BS) {
             const int r = e % n, q = e / n;
             copy16(X + ((size_t)(k0 / V + q) * n + r) * V, P + r * LDP + q * V);
         }
-        for (int e = tid; e < NB * nvb; e += BS) {
-            const int kk = e % NB, cb = e / NB;
-            if (cb >= k0 / V && cb < (k0 + NB) / V) continue;
-            copy16(Bp + kk * ldb + cb * V, X + ((size_t)cb * n + s_src[k0 + kk]) * V);
-        }
-        __syncthreads();
 
         // rank-NB update of every other column, one 16-column stripe per wave
         const int rt0 = ((k0 + NB) / 16) % nrt;
         for (int s = wave; s < nstripe; s += W) {
             const int c0 = (s < k0 / 16 ? s : s + NB / 16) * 16;
+            // the stripe's entries of the pivot rows, read before the stripe
+            // is overwritten
             T aop[KQ];
 #pragma unroll
-            for (int kc = 0; kc < KQ; ++kc) aop[kc] = Bp[(g * KQ + kc) * ldb + c0 + mfma_row(T(), li)];
+            for (int kc = 0; kc < KQ; ++kc)
+                aop[kc] = X[xoff<T>(n, s_src[k0 + g * KQ + kc], c0 + mfma_row(T(), li))];
             for (int i = 0; i < nrt; i += U) {
                 Q acc[U];
                 int row[U];
@@ -445,9 +566,9 @@ __global__ __launch_bounds__(BS) void k_gj_invert(Slab S, int j0) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     T bop[KQ];
-                    const T *pr = P + row[u] * LDP + g * KQ;
+                    const T *pr2 = P + row[u] * LDP + g * KQ;
 #pragma unroll
-                    for (int kc = 0; kc < KQ; kc += V) copy16(bop + kc, pr + kc);
+                    for (int kc = 0; kc < KQ; kc += V) copy16(bop + kc, pr2 + kc);
 #pragma unroll
                     for (int kc = 0; kc < KQ; ++kc) acc[u] = mfma16(aop[kc], bop[kc], acc[u]);
                 }
@@ -462,7 +583,7 @@ __global__ __launch_bounds__(BS) void k_gj_invert(Slab S, int j0) {
     for (int t = 0; t < SC; ++t)
         if (tid + t * BS < n) s_sig[tid + t * BS] = sig[t];
     const int ldl = n + 1;
-    const int rb = (n * LDP + NB * ldb) / ldl;
+    const int rb = n * LDP / ldl;
     T *L = P;
     __syncthreads();
     for (int r0 = 0; r0 < n; r0 += rb) {
@@ -484,11 +605,11 @@ __global__ __launch_bounds__(BS) void k_gj_invert(Slab S, int j0) {
     }
 }
 
-// Dynamic LDS of k_gj_invert: the panel and the gathered pivot rows.
+// Dynamic LDS of k_gj_invert: the panel.
 template <typename T, int NB>
 static size_t gj_lds_bytes(int n) {
     constexpr int V = 16 / (int)sizeof(T);
-    return ((size_t)n * (NB + V) + (size_t)NB * (n + 16)) * sizeof(T);
+    return (size_t)n * (NB + V) * sizeof(T);
 }
 
 template <typename T, int NB, int BS>
@@ -499,6 +620,8 @@ static hipError_t launch_gj(const Slab &S, int j0, int nb, hipStream_t st) {
     if (e != hipSuccess) return e;
     const size_t dyn = gj_lds_bytes<T, NB>(S.np);
     if (dyn + a.sharedSizeBytes > 160 * 1024) return hipErrorInvalidValue;
+    if ((size_t)(S.N + S.G * S.G) * sizeof(double) > dyn) return hipErrorInvalidValue;  // assembly staging
+    if (S.np > BS) return hipErrorInvalidValue;                                         // a row per thread
     e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_gj_invert<T, NB, BS>), dim3(nb), dim3(BS), dyn, st, S, j0);
