@@ -38,8 +38,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X_HBM_GBS = 8000.0       # published HBM3E peak, GB/s
-MI355X_FP32_TFLOPS = 157.3    # published FP32 vector peak
-MI355X_FP64_TFLOPS = 78.6     # published FP64 vector peak
+MI355X_FP32_TFLOPS = 157.3    # published FP32 vector peak (FP32 matrix: the same figure)
+MI355X_FP64_TFLOPS = 78.6     # published FP64 vector peak (FP64 matrix: the same figure)
 
 
 def parse():
@@ -117,7 +117,8 @@ def run_method(probs, method, precision, K, W_, tol, torch, B, autotune=True):
     per = [dict(dt=p["dt"], setup_s=setup_s[i], iterations_per_step=float(its[:, i].mean()),
                 iterations_max=int(its[:, i].max())) for i, p in enumerate(probs)]
     return dict(time_s=max(gpu_ms / 1e3, 1e-12), cell_solves=cell_solves, per=per, status=status,
-                kernel=kern, configs=configs)
+                kernel=kern, configs=configs,
+                setup=setup_model(probs, setup_s, precision == B.OCI_FP32_REFINED))
 
 
 def summary(r, label, K, keys):
@@ -129,7 +130,7 @@ def summary(r, label, K, keys):
                 setup_s={k: round(x["setup_s"], 4) for x, k in zip(r["per"], keys)},
                 timed_region_s=round(r["time_s"], 6), ms_per_bench_step=round(r["time_s"] * 1e3 / K, 4),
                 kernel_ms=round(sum(k[0] for k in r["kernel"]), 3), status=r["status"],
-                launch_shape=r["configs"][0], label=label)
+                launch_shape=r["configs"][0], label=label, setup=r["setup"])
 
 
 def recorded_traffic(label):
@@ -149,6 +150,32 @@ def recorded_traffic(label):
     return float(t.group(1))
 
 
+def padded(n):
+    np_ = 8
+    while np_ < n:
+        np_ *= 2
+    return np_
+
+
+def setup_model(probs, setup_s, fp32):
+    """Cell inversion at setup: 2 np^3 flops per cell (LU + inversion, or the
+    same count as blocked Gauss-Jordan), over the wall time of oci_setup
+    (uploads, assembly, inversion and the SI precompute).  Cells with
+    np >= 128 run the MFMA kernel; its peak is the matrix peak of the type."""
+    flop = sum(2.0 * padded(4 * p["N"] * p["G"]) ** 3 * p["J"] for p in probs)
+    secs = float(sum(setup_s))
+    tf = flop / max(secs, 1e-12) / 1e12
+    peak = MI355X_FP32_TFLOPS if fp32 else MI355X_FP64_TFLOPS
+    nps = sorted({padded(4 * p["N"] * p["G"]) for p in probs})
+    t = "float" if fp32 else "double"
+    kern = [f"k_gj_invert<{t},{32 if fp32 else 16},{512 if q >= 512 else 256}>" if q >= 128
+            else f"k_assemble_factor<{t}>" for q in nps]
+    return dict(bound="mfma" if nps[-1] >= 128 else "alu", achieved=round(tf, 3), peak=peak, unit="TFLOP/s",
+                frac=round(tf / peak, 4),
+                seconds=round(secs, 4), flop=flop, kernels=kern,
+                note="wall time of oci_setup (host uploads and synchronisation included)")
+
+
 def roofline_for(prim, probs, fp32):
     """Roofline of the dominant kernel (the persistent OCI kernel of the
     measured path, one launch per time step).
@@ -166,9 +193,7 @@ def roofline_for(prim, probs, fp32):
     p = probs[0]
     N, G = p["N"], p["G"]
     n = 4 * N * G
-    np_ = 8
-    while np_ < n:
-        np_ *= 2
+    np_ = padded(n)
     kern_ms = sum(k[0] for k in prim["kernel"])
     launches = sum(k[1] for k in prim["kernel"])
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
@@ -271,6 +296,12 @@ def batch_main(a, torch, B):
     J = np.array([p["J"] for p in probs])
     cell_solves = int((its * J[None, :]).sum())
     value = cell_solves / r["time_s"]
+    # factor stream of the batched kernel: each slab's FP32-refined bytes per
+    # cell-iteration (as for one slab) times its cell-iterations, over the
+    # replayed graph's time (the small per-step kernels included)
+    bpc = np.array([4 * n * n + 4 * n + 128 * p["N"] * p["G"] + 64 * p["G"]
+                    for p, n in ((p, 4 * p["N"] * p["G"]) for p in probs)], dtype=np.float64)
+    gbs = float((its * J[None, :] * bpc[None, :]).sum()) / r["time_s"] / 1e9
     out = {
         "metric": "cell-solves/s and s per converged step: FP32-refined vs FP64 OCI vs SI @1e-10",
         "value": round(value, 1), "unit": "cell-solves/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
@@ -281,8 +312,13 @@ def batch_main(a, torch, B):
                                f"n in {sorted({4 * p['N'] * p['G'] for p in probs})}, dt 1e-3, "
                                f"{K} graph-captured batched steps", "slabs": len(probs),
                    "cells": int(J.sum())},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": MI355X_HBM_GBS, "unit": "GB/s",
+                     "frac": round(gbs / MI355X_HBM_GBS, 4), "traffic": None, "kernel": "k_oci_batch<float,256>",
+                     "note": "algorithmic factor-stream bytes of every slab's cell-iterations over the "
+                             "replayed graph time (per-step bookkeeping kernels included)"},
         "batch": {"setup_s": round(r["setup_s"], 3), "workgroups": r["geometry"][0],
-                  "iterations_per_step_max": int(its.max()), "status": sorted(status)},
+                  "iterations_per_step_max": int(its.max()), "status": sorted(status),
+                  "setup": setup_model(probs, [r["setup_s"]], True)},
     }
     if not a.no_comparators:
         t_seq = 0.0

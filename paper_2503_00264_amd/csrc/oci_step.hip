@@ -282,8 +282,31 @@ __device__ inline void lc_row(const Slab &S, int j, int g, double mu, int u, dou
 // the inverse in registers, and the row's constants in LDS, for the whole
 // step (one tile per workgroup); BS: threads per workgroup.  At most 128
 // VGPRs (4 waves per SIMD).
+// LDS of one workgroup of the global iteration body.  A kernel provides it as
+// raw bytes, so that kernels holding several bodies (one per cell size) can
+// overlay them.
 template <typename T, int NP, bool RES, int BS>
-__device__ inline void oci_global_body(const Slab &S, const StepIO &io, int ntiles, int wg, unsigned nwg) {
+struct GlobalLds {
+    static constexpr bool REF = sizeof(T) == 4;
+    static constexpr int RPT = NP > BS ? NP / BS : 1;
+    static constexpr int CPT = BS / (NP / RPT);
+    static constexpr bool CACHE = RES && REF;
+    __align__(16) T vec[CPT][NP];
+    double psi[REF ? CPT : 1][REF ? NP : 1];
+    double wx[CPT][NP];
+    double phi[REF ? CPT : 1][REF ? NP / 2 : 1];
+    double coef[CACHE ? CPT : 1][CACHE ? NP : 1][4];
+    double crow[CACHE ? CPT : 1][CACHE ? NP : 1];
+    double scat[CACHE ? CPT : 1][CACHE ? NP / 8 * NP / 8 : 1];
+    double mu[NP / 4], w[NP / 4];
+    double tmp[BS / 64 + 1];
+    double mx[BS / 64];
+    int flag[4];
+};
+
+template <typename T, int NP, bool RES, int BS>
+__device__ __attribute__((always_inline)) inline void oci_global_body(const Slab &S, const StepIO &io, int ntiles, int wg,
+                                                                 unsigned nwg, unsigned char *lds_raw) {
     constexpr bool REF = sizeof(T) == 4;
     constexpr int RPT = NP > BS ? NP / BS : 1;   // rows per thread
     constexpr int TPC = NP / RPT;                 // threads per cell
@@ -293,17 +316,20 @@ __device__ inline void oci_global_body(const Slab &S, const StepIO &io, int ntil
     constexpr bool CACHE = RES && REF;            // row constants cached in LDS
     typedef typename Vec16<T>::type VT;
 
-    __shared__ __align__(16) T s_vec[CPT][NP];
-    __shared__ double s_psi[REF ? CPT : 1][REF ? NP : 1];
-    __shared__ double s_wx[CPT][NP];
-    __shared__ double s_phi[REF ? CPT : 1][REF ? NP / 2 : 1];
-    __shared__ double s_coef[CACHE ? CPT : 1][CACHE ? NP : 1][4];
-    __shared__ double s_crow[CACHE ? CPT : 1][CACHE ? NP : 1];
-    __shared__ double s_scat[CACHE ? CPT : 1][CACHE ? NP / 8 * NP / 8 : 1];
-    __shared__ double s_mu[NP / 4], s_w[NP / 4];
-    __shared__ double s_tmp[BS / 64 + 1];
-    __shared__ double s_max[BS / 64];
-    __shared__ int s_flag[4];
+    typedef GlobalLds<T, NP, RES, BS> Lds;
+    Lds &lds = *reinterpret_cast<Lds *>(lds_raw);
+    auto &s_vec = lds.vec;
+    auto &s_psi = lds.psi;
+    auto &s_wx = lds.wx;
+    auto &s_phi = lds.phi;
+    auto &s_coef = lds.coef;
+    auto &s_crow = lds.crow;
+    auto &s_scat = lds.scat;
+    auto &s_mu = lds.mu;
+    auto &s_w = lds.w;
+    auto &s_tmp = lds.tmp;
+    auto &s_max = lds.mx;
+    auto &s_flag = lds.flag;
 
     const int tid = threadIdx.x;
     const int cl = tid / TPC;
@@ -519,7 +545,8 @@ __device__ inline void oci_global_body(const Slab &S, const StepIO &io, int ntil
 template <typename T, int NP, bool RES, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
 void k_oci_step(Slab S, StepIO io, int ntiles) {
-    oci_global_body<T, NP, RES, BS>(S, io, ntiles, blockIdx.x, gridDim.x);
+    __shared__ __align__(16) unsigned char s_lds[sizeof(GlobalLds<T, NP, RES, BS>)];
+    oci_global_body<T, NP, RES, BS>(S, io, ntiles, blockIdx.x, gridDim.x, s_lds);
 }
 
 // Relaxed agent-scope accesses: coherent across the XCDs without any L2
@@ -1562,6 +1589,8 @@ __global__ __launch_bounds__(kBlock) void k_si_flux(Slab S) {
     }
 }
 
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+
 // ------------------------------------------------------------ batched slabs
 // Many independent slab problems (uneven J, N, G) in one persistent launch.
 // Slab k owns the workgroups [wg0, wg0 + nwg) of the grid; each runs the
@@ -1571,6 +1600,12 @@ __global__ __launch_bounds__(kBlock) void k_si_flux(Slab S) {
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
 void k_oci_batch(const BatchEntry *tab, int nslab) {
+    // one workgroup runs one body: their LDS overlays
+    constexpr size_t kLds = cmax(cmax(cmax(sizeof(GlobalLds<T, 8, false, BS>), sizeof(GlobalLds<T, 16, false, BS>)),
+                                      cmax(sizeof(GlobalLds<T, 32, false, BS>), sizeof(GlobalLds<T, 64, false, BS>))),
+                                 cmax(cmax(sizeof(GlobalLds<T, 128, false, BS>), sizeof(GlobalLds<T, 256, false, BS>)),
+                                      sizeof(GlobalLds<T, 512, false, BS>)));
+    __shared__ __align__(16) unsigned char s_lds[kLds];
     __shared__ int s_k;
     if (threadIdx.x == 0) {
         int lo = 0, hi = nslab - 1;     // last entry with wg0 <= blockIdx.x
@@ -1581,19 +1616,22 @@ void k_oci_batch(const BatchEntry *tab, int nslab) {
         s_k = lo;
     }
     __syncthreads();
-    const BatchEntry &e = tab[s_k];
+    // the slab's view stays in the table (read through the scalar cache): a
+    // local copy would sit in scratch memory, as the body indexes its
+    // ping-pong pointer arrays with the run-time buffer parity
+    const BatchEntry &e = tab[__builtin_amdgcn_readfirstlane(s_k)];
     const int lw = (int)blockIdx.x - e.wg0;
     if (lw < 0 || lw >= e.nwg) return;
-    const Slab S = e.S;
-    const StepIO io = e.io;
+    const Slab &S = e.S;
+    const StepIO &io = e.io;
     switch (S.np) {
-    case 8: oci_global_body<T, 8, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
-    case 16: oci_global_body<T, 16, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
-    case 32: oci_global_body<T, 32, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
-    case 64: oci_global_body<T, 64, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
-    case 128: oci_global_body<T, 128, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
-    case 256: oci_global_body<T, 256, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
-    case 512: oci_global_body<T, 512, false, BS>(S, io, e.ntiles, lw, e.nwg); break;
+    case 8: oci_global_body<T, 8, false, BS>(S, io, e.ntiles, lw, e.nwg, s_lds); break;
+    case 16: oci_global_body<T, 16, false, BS>(S, io, e.ntiles, lw, e.nwg, s_lds); break;
+    case 32: oci_global_body<T, 32, false, BS>(S, io, e.ntiles, lw, e.nwg, s_lds); break;
+    case 64: oci_global_body<T, 64, false, BS>(S, io, e.ntiles, lw, e.nwg, s_lds); break;
+    case 128: oci_global_body<T, 128, false, BS>(S, io, e.ntiles, lw, e.nwg, s_lds); break;
+    case 256: oci_global_body<T, 256, false, BS>(S, io, e.ntiles, lw, e.nwg, s_lds); break;
+    case 512: oci_global_body<T, 512, false, BS>(S, io, e.ntiles, lw, e.nwg, s_lds); break;
     default: break;
     }
 }
