@@ -78,6 +78,7 @@ def kernel_label(cfg, fp32, np_):
 def run_method(probs, method, precision, K, W_, tol, torch, B, autotune=True):
     """Set up one solver per problem, tune, warm up, reset, then time K steps."""
     solvers, setup_s, configs = [], [], []
+    B.Solver(probs[0], precision=precision, tol=tol).close()   # first-use costs out of the setup times
     for p in probs:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -133,18 +134,19 @@ def summary(r, label, K, keys):
                 launch_shape=r["configs"][0], label=label, setup=r["setup"])
 
 
-def recorded_traffic(label):
-    """HBM bytes per cell-iteration of `label` from the committed PMC summary,
-    valid only while the kernel source is the one the counters were taken on."""
+def recorded_traffic(label, summary="pmc_traffic_regions4096.md", figure="HBM bytes per cell-iteration"):
+    """A traffic figure of `label` from a committed PMC summary (HBM bytes per
+    cell-iteration, or per algorithmic byte), valid only while the kernel
+    source is the one the counters were taken on."""
     src = os.path.join(ROOT, "paper_2503_00264_amd", "csrc", "oci_step.hip")
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    path = os.path.join(ROOT, "profiles", "pmc_traffic_regions4096.md")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"source sha256\[:16\]: `([0-9a-f]+)`", text)
     k = re.search(r"kernel: `([^`]+)`", text)
-    t = re.search(r"HBM bytes per cell-iteration: ([0-9.]+)", text)
+    t = re.search(re.escape(figure) + r": ([0-9.]+)", text)
     if not (m and k and t) or m.group(1) != digest or k.group(1) != label:
         return None
     return float(t.group(1))
@@ -301,7 +303,10 @@ def batch_main(a, torch, B):
     # replayed graph's time (the small per-step kernels included)
     bpc = np.array([4 * n * n + 4 * n + 128 * p["N"] * p["G"] + 64 * p["G"]
                     for p, n in ((p, 4 * p["N"] * p["G"]) for p in probs)], dtype=np.float64)
-    gbs = float((its * J[None, :] * bpc[None, :]).sum()) / r["time_s"] / 1e9
+    alg_bytes = float((its * J[None, :] * bpc[None, :]).sum())
+    gbs = alg_bytes / r["time_s"] / 1e9
+    ratio = recorded_traffic("k_oci_batch<float,256>", "k_oci_batch_batch64.md", "HBM bytes per algorithmic byte")
+    traffic = None if ratio is None else round(ratio * alg_bytes / K, 1)
     out = {
         "metric": "cell-solves/s and s per converged step: FP32-refined vs FP64 OCI vs SI @1e-10",
         "value": round(value, 1), "unit": "cell-solves/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
@@ -313,7 +318,8 @@ def batch_main(a, torch, B):
                                f"{K} graph-captured batched steps", "slabs": len(probs),
                    "cells": int(J.sum())},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": MI355X_HBM_GBS, "unit": "GB/s",
-                     "frac": round(gbs / MI355X_HBM_GBS, 4), "traffic": None, "kernel": "k_oci_batch<float,256>",
+                     "frac": round(gbs / MI355X_HBM_GBS, 4), "traffic": traffic, "kernel": "k_oci_batch<float,256>",
+                     "avg_launch_us": round(r["time_s"] / K * 1e6, 1),
                      "note": "algorithmic factor-stream bytes of every slab's cell-iterations over the "
                              "replayed graph time (per-step bookkeeping kernels included)"},
         "batch": {"setup_s": round(r["setup_s"], 3), "workgroups": r["geometry"][0],
