@@ -49,6 +49,12 @@ def _cases():
         "odd_N6_n24": (W.regions(seed=6, J=77, N=6, n_regions=7, length=3.0, dt=0.2), 2),
         "G3_n48": (W.multigroup(seed=7, J=45, N=4, G=3, n_regions=5, length=2.0,
                                 speeds=(5.0, 1.0, 0.2), dt=0.3), 2),
+        # identity-padded blocks in the large-cell setup kernel: n = 120 in a
+        # 128 block, n = 192 in a 256 block
+        "G3_N10_n120": (W.multigroup(seed=9, J=24, N=10, G=3, n_regions=4, length=1.0,
+                                     speeds=(50.0, 5.0, 0.5), dt=0.01), 2),
+        "G3_N16_n192": (W.multigroup(seed=10, J=16, N=16, G=3, n_regions=4, length=0.5,
+                                     speeds=(50.0, 5.0, 0.5), dt=0.01), 2),
         "single_cell": (W.multigroup(seed=8, J=1, N=8, G=2, n_regions=1, length=0.5,
                                      speeds=(2.0, 1.0), dt=0.1), 2),
         "N2_J5": (W.homogeneous(J=5, N=2, length=1.0), 2),
@@ -91,7 +97,8 @@ def test_si_fp64_lockstep(name):
 
 
 @pytest.mark.parametrize("name", ["homogeneous64_n32", "regions512_n64", "multigroup192_n128",
-                                  "multigroup128_n256", "multigroup40_n512", "G3_n48"])
+                                  "multigroup128_n256", "multigroup40_n512", "G3_n48", "G3_N10_n120",
+                                  "G3_N16_n192"])
 def test_oci_refined_converges_to_oracle(name):
     p, steps = CASES[name]
     _announce(name, p, "oci fp32-refined converged")
