@@ -8,9 +8,12 @@ in 64 random regions (sigma_t ~ U[0.1, 10], c ~ U[0.5, 0.999], seed 2), S16
 zero initial flux, for each time-step size of the sweep {0.1, 0.01, 1e-3,
 1e-4} s.  One benchmark step = one converged time step of every problem of the
 sweep (four OCI time steps).  K steps reproduce K time steps of the workload
-from zero initial flux (the state is reset after the W warm-up steps); setup
-(device assembly + LU + inversion, then the launch-shape autotuner) happens
-before the timed region and is reported separately.
+from zero initial flux (the state is reset after the W warm-up steps): each
+problem's K OCI steps are one oci_run_steps call (one launch of the
+register-resident kernel, which turns each converged step over to the next
+itself), SI runs K si_step calls.  Setup (device assembly + LU + inversion,
+then the launch-shape autotuner) happens before the timed region and is
+reported separately.
 
 Other workloads: "homogeneous64", "multigroup8192", "multigroup16384" (one
 problem each), and "batch64": the 64 uneven slabs advanced together by the
@@ -93,23 +96,30 @@ def run_method(probs, method, precision, K, W_, tol, torch, B, autotune=True):
         for _ in range(W_):
             s.step(method)
         s.set_state(None)      # back to zero initial flux and a fresh first iterate
-    infos = torch.zeros((K, len(solvers), 32), dtype=torch.uint8, device=solvers[0].dev)
+    infos = torch.zeros((len(solvers), K, 24), dtype=torch.uint8, device=solvers[0].dev)
+    phis = [torch.empty((K,) + tuple(s.phi.shape), dtype=torch.float64, device=s.dev) for s in solvers]
     for s in solvers:
         B.oci_profile_enable(s.h, True)
-    fn = B.oci_step if method == "oci" else B.si_step
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
-    for k in range(K):
+    if method == "oci":
+        # K time steps per problem in one call (one launch on the
+        # register-resident kernel, K oci_step launches otherwise)
         for i, s in enumerate(solvers):
-            fn(s.h, s.q, s.inc_l, s.inc_r, s.phi, None, infos[k, i])
+            B.oci_run_steps(s.h, K, s.q, s.inc_l, s.inc_r, phis[i], None, infos[i])
+    else:
+        for k in range(K):
+            for i, s in enumerate(solvers):
+                B.si_step(s.h, s.q, s.inc_l, s.inc_r, phis[i][k], None, infos[i, k])
     ev1.record()
     torch.cuda.synchronize()
     gpu_ms = ev0.elapsed_time(ev1)
-    kern = [B.oci_profile_read(s.h) for s in solvers]
+    kern = [B.oci_profile_read(s.h) for s in solvers]            # (ms, steps) per problem
+    launches = [1 if (method == "oci" and c["local"] and c["resident"]) else K for c in configs]
     inf = infos.cpu().numpy()
-    dec = [[B.decode_info(inf[k, i]) for i in range(len(solvers))] for k in range(K)]
+    dec = [[B.decode_info(inf[i, k]) for i in range(len(solvers))] for k in range(K)]
     for s in solvers:
         s.close()
     its = np.array([[d["iterations"] for d in row] for row in dec])       # [K][problems]
@@ -118,7 +128,7 @@ def run_method(probs, method, precision, K, W_, tol, torch, B, autotune=True):
     per = [dict(dt=p["dt"], setup_s=setup_s[i], iterations_per_step=float(its[:, i].mean()),
                 iterations_max=int(its[:, i].max())) for i, p in enumerate(probs)]
     return dict(time_s=max(gpu_ms / 1e3, 1e-12), cell_solves=cell_solves, per=per, status=status,
-                kernel=kern, configs=configs,
+                kernel=kern, launches=launches, configs=configs,
                 setup=setup_model(probs, setup_s, precision == B.OCI_FP32_REFINED))
 
 
@@ -180,7 +190,8 @@ def setup_model(probs, setup_s, fp32):
 
 def roofline_for(prim, probs, fp32):
     """Roofline of the dominant kernel (the persistent OCI kernel of the
-    measured path, one launch per time step).
+    measured path: one launch per problem for all K steps when its rows are
+    register-resident, one per time step otherwise).
 
     Streamed inverse rows: bound by memory; algorithmic bytes per
     cell-iteration are the factor stream plus iterate, edge, source and flux
@@ -197,7 +208,7 @@ def roofline_for(prim, probs, fp32):
     n = 4 * N * G
     np_ = padded(n)
     kern_ms = sum(k[0] for k in prim["kernel"])
-    launches = sum(k[1] for k in prim["kernel"])
+    launches = sum(prim["launches"])
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
     bpc = (4 * n * n + 4 * n + 128 * N * G + 64 * G) if fp32 else (8 * n * n + 4 * n + 96 * N * G + 64 * G)
     fpc = 2 * n * n

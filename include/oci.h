@@ -149,6 +149,22 @@ int oci_step(oci_handle *h, const double *q_dev, const double *inc_left_dev,
              const double *inc_right_dev, double *phi_out_dev, double *psi_out_dev,
              oci_step_info *info_dev);
 
+/* nsteps consecutive OCI time steps with the same sources and incident
+ * fluxes (time-independent Q and boundary data, as in section 3 of the
+ * paper); the same result, step for step, as nsteps calls of oci_step.
+ *   phi_out_dev   [nsteps][J][G][4] scalar flux of each step's last iterate
+ *   psi_out_dev   [J][G][N][4] angular flux of the last step's last iterate,
+ *                 NULL = skip
+ *   info_dev      nsteps oci_step_info records in device memory
+ * With the register-resident kernel (see oci_get_config) the steps run in one
+ * launch: each step's stop turns the iterate over to the next step inside the
+ * kernel, so the inverse rows are loaded once for all of them.  Otherwise it
+ * calls oci_step nsteps times.  OCI_ERR_INVALID if nsteps < 1 or an output is
+ * NULL. */
+int oci_run_steps(oci_handle *h, int32_t nsteps, const double *q_dev, const double *inc_left_dev,
+                  const double *inc_right_dev, double *phi_out_dev, double *psi_out_dev,
+                  oci_step_info *info_dev);
+
 /* One source-iteration time step (Appendix A, Algorithm 1) on the same state
  * and with the same arguments as oci_step. */
 int si_step(oci_handle *h, const double *q_dev, const double *inc_left_dev,

@@ -25,7 +25,7 @@ OCI_NORM_SCALAR, OCI_NORM_ANGULAR = 0, 1
 
 # every symbol include/oci.h declares
 EXPORTS = ("oci_workspace_bytes", "oci_setup", "oci_set_state", "oci_get_state",
-           "oci_step", "si_step", "oci_profile_enable", "oci_profile_read",
+           "oci_step", "oci_run_steps", "si_step", "oci_profile_enable", "oci_profile_read",
            "oci_autotune", "oci_get_config", "oci_destroy", "oci_batch_workspace_bytes", "oci_batch_setup", "oci_batch_bind",
            "oci_batch_step", "oci_batch_capture", "oci_batch_replay", "oci_batch_set_state",
            "oci_batch_get_state", "oci_batch_rebalance", "oci_batch_info", "oci_batch_destroy", "oci_status_string")
@@ -69,6 +69,7 @@ def lib():
         L.oci_set_state.argtypes = [vp, vp]
         L.oci_get_state.argtypes = [vp, vp]
         L.oci_step.argtypes = [vp] * 7
+        L.oci_run_steps.argtypes = [vp, i32] + [vp] * 6
         L.si_step.argtypes = [vp] * 7
         L.oci_profile_enable.argtypes = [vp, i32]
         L.oci_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
@@ -155,6 +156,11 @@ def oci_get_state(h, psi_prev):
 def oci_step(h, q, inc_left, inc_right, phi_out, psi_out, info):
     return _check("oci_step", lib().oci_step(h, _ptr(q), _ptr(inc_left), _ptr(inc_right),
                                              _ptr(phi_out), _ptr(psi_out), _ptr(info)))
+
+
+def oci_run_steps(h, nsteps, q, inc_left, inc_right, phi_out, psi_out, info):
+    return _check("oci_run_steps", lib().oci_run_steps(h, nsteps, _ptr(q), _ptr(inc_left), _ptr(inc_right),
+                                                       _ptr(phi_out), _ptr(psi_out), _ptr(info)))
 
 
 def si_step(h, q, inc_left, inc_right, phi_out, psi_out, info):
@@ -334,6 +340,18 @@ class Solver:
         self.stream.synchronize()
         return (self.torch.stack(phis).cpu().numpy(),
                 [decode_info(i.cpu().numpy()) for i in infos])
+
+    def run_steps(self, steps=None, want_psi=False):
+        """`steps` OCI steps in one oci_run_steps call; the same returns as run()."""
+        steps = self.prob["steps"] if steps is None else steps
+        t = self.torch
+        phis = t.empty((steps,) + tuple(self.phi.shape), dtype=t.float64, device=self.dev)
+        infos = t.zeros((steps, 24), dtype=t.uint8, device=self.dev)
+        oci_run_steps(self.h, steps, self.q, self.inc_l, self.inc_r, phis,
+                      self.psi if want_psi else None, infos)
+        self.stream.synchronize()
+        raw = infos.cpu().numpy()
+        return phis.cpu().numpy(), [decode_info(raw[k]) for k in range(steps)]
 
     def autotune(self, iters=8):
         """Pick the fastest launch shape (state is zero afterwards)."""

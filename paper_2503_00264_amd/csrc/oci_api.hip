@@ -58,6 +58,7 @@ struct oci_handle {
     bool profiling;
     std::vector<hipEvent_t> ev_pool;   // recorded pairs: [2k] start, [2k+1] stop
     size_t ev_used;
+    int32_t prof_steps;                // time steps those pairs cover
 };
 
 // Two events bracketing the iteration kernels of one step (instrumentation).
@@ -426,7 +427,41 @@ extern "C" int oci_step(oci_handle *h, const double *q_dev, const double *inc_le
     else
         HIPCHECK(launch_oci_step(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->st, true));
     if (e1) HIPCHECK(hipEventRecord(e1, h->st));
+    if (e1) h->prof_steps += 1;
     HIPCHECK(launch_end(h->S, io, h->st));
+    return OCI_OK;
+}
+
+extern "C" int oci_run_steps(oci_handle *h, int32_t nsteps, const double *q_dev, const double *inc_left_dev,
+                             const double *inc_right_dev, double *phi_out_dev, double *psi_out_dev,
+                             oci_step_info *info_dev) {
+    if (nsteps < 1) return OCI_ERR_INVALID;
+    int rc = check_step_args(h, phi_out_dev, info_dev);
+    if (rc) return rc;
+    const size_t phi_stride = (size_t)h->d.J * h->d.G * 4;
+    if (!(h->local && h->resident) || nsteps == 1) {
+        for (int k = 0; k < nsteps; ++k) {
+            rc = oci_step(h, q_dev, inc_left_dev, inc_right_dev, phi_out_dev + k * phi_stride,
+                          k == nsteps - 1 ? psi_out_dev : nullptr, info_dev + k);
+            if (rc) return rc;
+        }
+        return OCI_OK;
+    }
+    // one launch of the register-resident kernel for all steps; the first
+    // step opens and the last closes as in oci_step, the others turn over
+    // inside the kernel
+    StepIO io{q_dev, inc_left_dev, inc_right_dev, phi_out_dev, nullptr, info_dev, nsteps};
+    if (h->need_broadcast) HIPCHECK(launch_begin(h->S, io, true, h->st, h->nwg));
+    else HIPCHECK(launch_open(h->S, io, h->st, h->nwg));
+    h->need_broadcast = false;
+    hipEvent_t e0 = h->profiling ? prof_event(h) : nullptr, e1 = h->profiling ? prof_event(h) : nullptr;
+    if (e0) HIPCHECK(hipEventRecord(e0, h->st));
+    HIPCHECK(launch_oci_local(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->dyn_lds, h->st));
+    if (e1) HIPCHECK(hipEventRecord(e1, h->st));
+    if (e1) h->prof_steps += nsteps;
+    const StepIO last{q_dev, inc_left_dev, inc_right_dev, phi_out_dev + (nsteps - 1) * phi_stride, psi_out_dev,
+                      info_dev + (nsteps - 1), 1};
+    HIPCHECK(launch_end(h->S, last, h->st));
     return OCI_OK;
 }
 
@@ -454,6 +489,7 @@ extern "C" int si_step(oci_handle *h, const double *q_dev, const double *inc_lef
         if (batch < 64) batch *= 2;
     }
     if (e1) HIPCHECK(hipEventRecord(e1, h->st));
+    if (e1) h->prof_steps += 1;
     HIPCHECK(launch_end(h->S, io, h->st));
     return OCI_OK;
 }
@@ -462,6 +498,7 @@ extern "C" int oci_profile_enable(oci_handle *h, int on) {
     if (!h) return OCI_ERR_INVALID;
     h->profiling = on != 0;
     h->ev_used = 0;
+    h->prof_steps = 0;
     return OCI_OK;
 }
 
@@ -475,8 +512,9 @@ extern "C" int oci_profile_read(oci_handle *h, double *ms, int32_t *steps) {
         tot += t;
     }
     *ms = tot;
-    *steps = (int32_t)(h->ev_used / 2);
+    *steps = h->prof_steps;
     h->ev_used = 0;
+    h->prof_steps = 0;
     return OCI_OK;
 }
 

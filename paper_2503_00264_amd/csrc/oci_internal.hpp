@@ -98,6 +98,8 @@ struct StepIO {
     double *phi_out;             // [J][G][4]
     double *psi_out;             // [J][G][N][4] or null
     void *info;                  // oci_step_info*
+    int32_t nsteps;              // time steps in one launch (register-resident kernel; <= 1: one);
+                                 // phi_out and info then hold one record per step
 };
 
 // One slab of a batch: its view, its step inputs/outputs, and the block of

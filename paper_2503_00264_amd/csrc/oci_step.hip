@@ -1075,6 +1075,66 @@ enum : int {
 };
 }
 
+// End of an inner time step of a multi-step launch of k_oci_res: the step's
+// outputs (phi and its report), the next step's first iterate (the final one,
+// Psi^(fl) in D, copied to the LDS copy Q of iteration nl0, with its phi
+// summed as k_step_open sums it), the constant
+// part of b after the time update psi_(k-1/2) <- psi_(k+1/2) (eq. rhs_sg,
+// with the boundary sources as in the prologue), and the range's end edges
+// of that iterate tagged nl0.  psi_(k-1/2) itself is written by the launch's
+// last step only.  Every thread of the workgroup calls it (two workgroup
+// barriers).
+template <int BS>
+__device__ __attribute__((always_inline)) inline void res_next_step(const Slab &S, const StepIO &io, int step, int iters, int nl0,
+                                                        int ri, int cl, int t, const double *D_psi,
+                                                        const double *D_phi, double *Q_psi, double *Q_phi,
+                                                        double *crow, int ldc, const double *mu_tab,
+                                                        const double *dec, int c0, int c1, int wg, unsigned nwg) {
+    const int tid = threadIdx.x;
+    const int J = S.J, G = S.G, n = S.n, nh = S.N / 2, NG = S.N * S.G;
+    const int totf = (c1 - c0) * 4 * G, totp = (c1 - c0) * n;
+    double *fo = io.phi_out + ((size_t)step * J + c0) * 4 * G;
+    for (int k = tid; k < totf; k += BS) fo[k] = D_phi[k];
+    if (wg == 0 && tid == 0) {
+        char *rec = reinterpret_cast<char *>(io.info) + (size_t)step * 24;   // oci_step_info
+        const int err = __hip_atomic_load(&S.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        reinterpret_cast<int32_t *>(rec)[0] = iters;
+        reinterpret_cast<int32_t *>(rec)[1] = err ? -6 : (int)dec[1];
+        reinterpret_cast<double *>(rec)[1] = dec[2];
+        reinterpret_cast<double *>(rec)[2] = dec[3];
+    }
+    for (int k = tid; k < totp; k += BS) Q_psi[k] = D_psi[k];
+    // phi of the first iterate summed over m in order, as a step opened by
+    // k_step_open has it
+    for (int k = tid; k < totf; k += BS) {
+        const int u = k & 3, cg = k >> 2;   // cg = cell * G + g
+        const double *p = D_psi + (size_t)cg * S.N * 4 + u;
+        double f = 0.0;
+        for (int m = 0; m < S.N; ++m) f += S.w[m] * p[m * 4];
+        Q_phi[k] = f;
+    }
+    __syncthreads();
+    if (ri & res::LIVE) {
+        const int m = ri & 0xFF, g = (ri >> 8) & 0xFF, u = (ri >> 16) & 3, lev = u >> 1;
+        const int j = c0 + cl;
+        const double mu = mu_tab[m], dx = S.dx[j];
+        const size_t jg = (size_t)j * G + g;
+        double c = io.q ? 0.25 * dx * io.q[jg * 4 + u] : 0.0;
+        if (u < 2) c += dx / (2.0 * S.speed[g] * S.dt) * Q_psi[(size_t)cl * n + t + 2];
+        if ((ri & res::INL) && (ri & res::BND) && io.inc_l) c += mu * io.inc_l[((size_t)lev * G + g) * nh + (m - nh)];
+        if ((ri & res::INR) && (ri & res::BND) && io.inc_r) c -= mu * io.inc_r[((size_t)lev * G + g) * nh + m];
+        crow[(size_t)cl * ldc + t] = c;
+        const double x = Q_psi[(size_t)cl * n + t];
+        uint64_t *ex = reinterpret_cast<uint64_t *>(S.exch);
+        auto slot = [&](int side, int mm) -> uint64_t * {
+            return ex + 2 * ((((size_t)(nl0 & 1) * nwg + wg) * 2 + side) * NG + ((size_t)lev * G + g) * nh + mm);
+        };
+        if (ri & res::OUTL) put_edge(slot(0, m), x, nl0);
+        if (ri & res::OUTR) put_edge(slot(1, m - nh), x, nl0);
+    }
+    __syncthreads();
+}
+
 template <typename T, int NP, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
 void k_oci_res(Slab S, StepIO io, int ntiles) {
@@ -1190,6 +1250,12 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
     constexpr int WSN = W >= 4 ? W - 2 : W;
     const int Sw = ((int)nwg + WSN - 1) / WSN;
     const int dec_wave = W / 2;
+    // Several time steps in one launch: iterations are numbered across the
+    // launch (the tags of edges and partials never repeat), and step `step`
+    // starts at iteration l0 from the iterate its predecessor stopped at.
+    __shared__ int s_step;   // steps finished in this launch (read at a stop only)
+    if (tid == 0) s_step = 0;
+    int l0 = 0;
 
     for (int l = 0;; ++l) {
         // re-derived every iteration from opaque copies, so the compiler keeps
@@ -1204,6 +1270,7 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
         double *Np = L_psi0 + ((size_t)nb * CPT + cl) * n;         // ... and Psi^(l+1)
         double *Nf = L_phi0 + ((size_t)nb * CPT + cl) * 4 * G;
         const int lp = l - LAG;                                   // iteration whose partials this one adds
+        const bool lpv = lp >= l0;                                // ... one of this step
         const uint64_t *part_prev = part_bits + (size_t)(lp & (kPartSlots - 1)) * nwg;
         int bad = 0;
 
@@ -1211,7 +1278,7 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
         // added before the barrier
         const int sh = (tq >> 6) - WS0;
         const int q0 = sh * Sw + (tq & 63);
-        const bool qon = lp >= 0 && sh >= 0 && sh < WSN && (tq & 63) < Sw && q0 < (int)nwg;
+        const bool qon = lpv && sh >= 0 && sh < WSN && (tq & 63) < Sw && q0 < (int)nwg;
         const uint64_t qv = qon ? ld_bits(part_prev + q0) : kSlotEmpty;
 
         // (1) b = constant part + lagged incident edge from a cell
@@ -1330,7 +1397,7 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
             }
             if ((tid & 63) == 0) s_part[l & 1][tid >> 6] = v;
         }
-        if (lp >= 0) {
+        if (lpv) {
             double v = 0.0;
             if (qon) {
                 auto wait_part = [&](uint64_t xq, int k) -> double {
@@ -1359,11 +1426,27 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
 
         // the decision taken after the previous barrier applies now; on a
         // stop the iterate it concerns, Psi^(l-LAG), is intact in its copy
-        if (l - 1 - LAG >= 0 && s_dec[(l + 1) & 1][0] != 0.0) {
-            const int iters = l - LAG;
+        if (l - 1 - LAG >= l0 && s_dec[(l + 1) & 1][0] != 0.0) {
+            const int fl = l - LAG;             // the final iterate (launch numbering)
+            const int iters = fl - l0;          // iterations of this step
+            const double *D_psi = L_psi0 + (size_t)((unsigned)fl % NCOPY) * CPT * n;
+            const double *D_phi = L_phi0 + (size_t)((unsigned)fl % NCOPY) * CPT * 4 * G;
+            const int step = s_step;
+            if (step + 1 < io.nsteps) {
+                // iterations l + 1 and l + 2 are skipped: the edge slots of
+                // parity l + 1 hold iterate l + 1's edges, which nobody reads,
+                // while those of parity l may still be waited for
+                const int nl0 = l + 3;
+                res_next_step<BS>(S, io, step, iters, nl0, ri, cl, t, D_psi, D_phi,
+                                  L_psi0 + (size_t)((unsigned)nl0 % NCOPY) * CPT * n,
+                                  L_phi0 + (size_t)((unsigned)nl0 % NCOPY) * CPT * 4 * G, &s_crow[0][0], NP, s_mu,
+                                  &s_dec[(l + 1) & 1][0], c0, c1, wg, nwg);
+                if (tid == 0) s_step = step + 1;   // read again only after the next step's barriers
+                l0 = nl0;
+                l = nl0 - 1;
+                continue;
+            }
             const int fin = (base + iters) & 1;
-            const double *D_psi = L_psi0 + (size_t)((unsigned)iters % NCOPY) * CPT * n;
-            const double *D_phi = L_phi0 + (size_t)((unsigned)iters % NCOPY) * CPT * 4 * G;
             double *pout = S.psi[fin] + (size_t)c0 * n;
             const int totp = (c1 - c0) * n;
             for (int k = tid; k < totp; k += BS) pout[k] = D_psi[k];
@@ -1382,14 +1465,14 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
             }
             return;
         }
-        if (lp >= 0 && (tid >> 6) == dec_wave) {
+        if (lpv && (tid >> 6) == dec_wave) {
             // the stopping rule (section 2.1) on e_(lp+1), from the shares
             // (every workgroup's decision wave adds the same values in the
             // same order)
             double tot = 0.0;
 #pragma unroll
             for (int w = 0; w < W; ++w) tot += s_psum[l & 1][w];
-            const int iters = lp + 1;
+            const int iters = lp + 1 - l0;
             const double e = sqrt(tot);
             const double rho = iters >= 2 ? e / s_eprev[(l + 1) & 1] : __builtin_nan("");
             int done = 0, status = OK;

@@ -257,3 +257,58 @@ def test_autotune_keeps_parity(name):
         if prec == B.OCI_FP64:
             want = oracle.Oracle(p).run("oci", steps=steps, fixed_iters=6)["phi"]
             assert rel(got, want) <= 1e-12
+
+
+def _multi_step_cases():
+    rng = np.random.default_rng(31)
+    b = W.multigroup(seed=9, J=96, N=8, G=2, n_regions=8, length=2.0, speeds=(3.0, 1.0), dt=0.2,
+                     steps=4)
+    b["inc_left"] = rng.uniform(0, 1, size=(2, 2, 4))
+    b["inc_right"] = rng.uniform(0, 1, size=(2, 2, 4))
+    b["psi_init"] = rng.uniform(0, 1, size=(96, 2, 8, 2))
+    return {
+        "homogeneous64_n32": W.config("homogeneous64"),
+        "regions512_n64": dict(CASES["regions512_n64"][0], steps=5),
+        "boundary_n64": b,
+        "multigroup128_n256": dict(CASES["multigroup128_n256"][0], steps=3),
+    }
+
+
+MULTI = _multi_step_cases()
+
+
+@pytest.mark.parametrize("prec", [B.OCI_FP64, B.OCI_FP32_REFINED])
+@pytest.mark.parametrize("name", list(MULTI))
+def test_run_steps_equals_single_steps(name, prec):
+    """Several steps in one launch (the register-resident kernel turns each
+    stop over to the next step itself) give bit for bit what one call per step
+    gives: fluxes, step reports and the final state."""
+    p = MULTI[name]
+    _announce(name, p, f"oci_run_steps vs oci_step, prec={prec}, steps={p['steps']}")
+    s = B.Solver(p, precision=prec, tol=1e-10)
+    want, winfo = s.run()
+    wstate = s.get_state().cpu().numpy()
+    resident = s.config()["resident"]
+    s.close()
+    s = B.Solver(p, precision=prec, tol=1e-10)
+    got, ginfo = s.run_steps()
+    gstate = s.get_state().cpu().numpy()
+    s.close()
+    if prec == B.OCI_FP32_REFINED and name != "multigroup128_n256":
+        assert resident, "the multi-step launch needs the register-resident kernel here"
+    assert ginfo == winfo
+    assert np.array_equal(got, want)
+    assert np.array_equal(gstate, wstate)
+
+
+def test_run_steps_lockstep_matches_oracle():
+    p = dict(W.config("homogeneous64"), steps=6)
+    _announce("homogeneous64", p, "oci_run_steps, fp64 lock-step K=9 against the oracle")
+    want = oracle.Oracle(p).run("oci", fixed_iters=9)["phi"]
+    s = B.Solver(p, precision=B.OCI_FP64, fixed_iters=9)
+    resident = s.config()["resident"]
+    got, infos = s.run_steps()
+    s.close()
+    assert resident, "n = 32 in FP64 runs the register-resident kernel"
+    assert all(i["iterations"] == 9 and i["status"] == 0 for i in infos), infos
+    assert rel(got, want) <= 1e-12
