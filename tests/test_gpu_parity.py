@@ -312,3 +312,26 @@ def test_run_steps_lockstep_matches_oracle():
     assert resident, "n = 32 in FP64 runs the register-resident kernel"
     assert all(i["iterations"] == 9 and i["status"] == 0 for i in infos), infos
     assert rel(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["not_converged", "nonfinite"])
+def test_run_steps_statuses_equal_single_steps(case):
+    p = dict(W.homogeneous(J=64, N=8), steps=3)
+    kw = dict(tol=1e-10)
+    if case == "not_converged":
+        kw["max_iters"] = 3
+    else:
+        q = p["q"].copy()
+        q[10, 0, 2] = np.nan
+        p["q"] = q
+    _announce("homogeneous64", p, f"oci_run_steps statuses: {case}")
+    out = []
+    for multi in (False, True):
+        s = B.Solver(p, precision=B.OCI_FP32_REFINED, **kw)
+        got, infos = s.run_steps() if multi else s.run()
+        s.close()
+        out.append((got, infos))
+    want = B.OCI_NOT_CONVERGED if case == "not_converged" else B.OCI_NONFINITE
+    assert all(i["status"] == want for i in out[1][1]), out[1][1]
+    assert [(i["iterations"], i["status"]) for i in out[0][1]] == [(i["iterations"], i["status"]) for i in out[1][1]]
+    assert np.array_equal(out[0][0], out[1][0], equal_nan=True)
