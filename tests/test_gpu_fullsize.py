@@ -8,6 +8,10 @@ uses (autotuned single-slab kernels; the batched launch for the 64 slabs).
   step (<= 1e-12), and, for FP64 and FP32-refined converged solutions, the
   corner-balance residual of tests/balance.py (a property of the discrete
   solution that holds at any size and does not involve the oracle).
+* multigroup16384, the precision form: the FP32-refined and the FP64 OCI
+  solutions of the first time step, converged to tol 1e-12 on the GPU, against
+  the oracle's converged truth (tol 1e-14): <= 1e-10 and <= 1e-12 normwise
+  relative (printed; about two minutes of CPU work for the oracle).
 * batch64: every slab of the batched launch satisfies the same residual
   property after a converged step.
 
@@ -91,6 +95,25 @@ def test_multigroup_full_size(name):
         print(f"  prec={prec}: {info}", flush=True)
         assert info["status"] == 0
         assert _residual_check(p, psi, np.zeros((p["J"], p["G"], p["N"], 2))) <= 1e-9
+
+
+def test_multigroup16384_precision_form_against_oracle():
+    p = dict(W.config("multigroup16384"), steps=1)
+    announce("multigroup16384", p, "first step converged: FP32-refined and FP64 against the oracle")
+    want = oracle.Oracle(p, methods=("oci",)).run("oci", steps=1, tol=1e-14)["phi"]
+    errs = {}
+    for prec in (B.OCI_FP32_REFINED, B.OCI_FP64):
+        s = B.Solver(p, precision=prec, tol=1e-12)
+        s.autotune(4)
+        got, infos = s.run(steps=1)
+        s.close()
+        torch.cuda.empty_cache()
+        assert infos[0]["status"] == 0, infos
+        errs[prec] = rel(got, want)
+        print(f"  prec={prec}: iterations {infos[0]['iterations']}, max relative phi error vs the oracle "
+              f"{errs[prec]:.3e}", flush=True)
+    assert errs[B.OCI_FP32_REFINED] <= 1e-10
+    assert errs[B.OCI_FP64] <= 1e-12
 
 
 def test_batch64_full_size_residual():
