@@ -1060,7 +1060,9 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
 // the iterate's predecessors in LDS (kResidentCopies in all): every wave other
 // than the two end ones adds a share of the partials of iteration l - LAG
 // before the barrier, one wave applies the rule after it, and the outcome
-// takes effect at the next barrier.
+// takes effect at the next barrier.  With io.nsteps > 1 one launch runs that
+// many time steps: each stop but the last turns the iterate over to the next
+// step inside the kernel (res_next_step), so the rows are loaded once.
 namespace res {
 enum : int {
     LIVE = 1 << 18,    // a row of a live cell (t < n, j < J)
@@ -1076,14 +1078,13 @@ enum : int {
 }
 
 // End of an inner time step of a multi-step launch of k_oci_res: the step's
-// outputs (phi and its report), the next step's first iterate (the final one,
-// Psi^(fl) in D, copied to the LDS copy Q of iteration nl0, with its phi
-// summed as k_step_open sums it), the constant
-// part of b after the time update psi_(k-1/2) <- psi_(k+1/2) (eq. rhs_sg,
-// with the boundary sources as in the prologue), and the range's end edges
-// of that iterate tagged nl0.  psi_(k-1/2) itself is written by the launch's
-// last step only.  Every thread of the workgroup calls it (two workgroup
-// barriers).
+// outputs (phi and its report), the next step's first iterate (the final
+// one, in D, copied to the LDS copy Q of iteration nl0, with its phi summed
+// as k_step_open sums it), the constant part of b after the time update
+// psi_(k-1/2) <- psi_(k+1/2) (eq. rhs_sg, with the boundary sources as in the
+// prologue), and the range's end edges of that iterate tagged nl0.
+// psi_(k-1/2) itself is written by the launch's last step only.  Every thread
+// of the workgroup calls it (two workgroup barriers).
 template <int BS>
 __device__ __attribute__((always_inline)) inline void res_next_step(const Slab &S, const StepIO &io, int step, int iters, int nl0,
                                                         int ri, int cl, int t, const double *D_psi,
@@ -1250,9 +1251,10 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
     constexpr int WSN = W >= 4 ? W - 2 : W;
     const int Sw = ((int)nwg + WSN - 1) / WSN;
     const int dec_wave = W / 2;
-    // Several time steps in one launch: iterations are numbered across the
-    // launch (the tags of edges and partials never repeat), and step `step`
-    // starts at iteration l0 from the iterate its predecessor stopped at.
+    // Several time steps in one launch (io.nsteps): iterations are numbered
+    // across the launch (the tags of edges and partials never repeat), and
+    // the current step starts at iteration l0 from the iterate its
+    // predecessor stopped at.
     __shared__ int s_step;   // steps finished in this launch (read at a stop only)
     if (tid == 0) s_step = 0;
     int l0 = 0;
