@@ -150,8 +150,9 @@ int oci_step(oci_handle *h, const double *q_dev, const double *inc_left_dev,
              oci_step_info *info_dev);
 
 /* nsteps consecutive OCI time steps with the same sources and incident
- * fluxes (time-independent Q and boundary data, as in section 3 of the
- * paper); the same result, step for step, as nsteps calls of oci_step.
+ * fluxes (time-independent Q and boundary data, as in the test problem of the
+ * paper's GPU performance study, section 3.2, table rosa_test); the same
+ * result, step for step, as nsteps calls of oci_step.
  *   phi_out_dev   [nsteps][J][G][4] scalar flux of each step's last iterate
  *   psi_out_dev   [J][G][N][4] angular flux of the last step's last iterate,
  *                 NULL = skip
