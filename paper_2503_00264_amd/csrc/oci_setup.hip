@@ -487,15 +487,14 @@ __global__ __launch_bounds__(BS) void k_gj_invert(Slab S, int j0) {
 #pragma unroll
             for (int q = 0; q < NB; q += V) get16(pn, q, &s_wr[par][bw][q]);
             const T inv = T(1) / pn[kk];
-            if (tid == p) {
-                pr = pn * inv;
-                pr[kk] = inv;
-                cand = false;
-            } else if (own) {
-                const T fi = pr[kk] * inv;
-                pr -= fi * pn;
-                pr[kk] = -fi;
-            }
+            // one branch-free update for every row: the pivot row (equal to
+            // pn) is scaled by 1/a, every other row loses fi times it; rows a
+            // thread does not own are never stored
+            const bool isp = tid == p;
+            const T fi = isp ? T(0) : pr[kk] * inv;
+            pr = (isp ? inv : T(1)) * pr - fi * pn;
+            pr[kk] = isp ? inv : -fi;
+            cand = cand && !isp;
             if (tid == 0) s_pl[kk] = p;
         }
 
