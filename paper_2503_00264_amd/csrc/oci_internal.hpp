@@ -30,7 +30,9 @@ constexpr int kPartTagBits = 4;
 // kernel keeps kResidentCopies = kResidentLag + 2 LDS copies of the range's
 // iterate.  A slot is rewritten kPartSlots iterations later, which needs
 // kPartSlots > kResidentLag + 1; the tag period 2^kPartTagBits exceeds
-// kPartSlots.
+// kPartSlots.  A multi-step launch skips iteration numbers at each step
+// turnover; it resets the skipped iterations' slots to kSlotEmpty, since a
+// value left there would carry the tag of the iteration 2^kPartTagBits later.
 constexpr int kPartSlots = 8;
 constexpr int kResidentLag = 2;
 constexpr int kResidentCopies = kResidentLag + 2;

@@ -1458,6 +1458,15 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
                 // parity l + 1 hold iterate l + 1's edges, which nobody reads,
                 // while those of parity l may still be waited for
                 const int nl0 = l + 3;
+                // iterations l .. l + 2 publish no partials, so their slots
+                // would still hold those of l - 8 .. l - 6, whose tags are
+                // the ones l + 8 .. l + 10 will carry: empty them (every
+                // reader of l - 8 .. l - 6 is done, since every workgroup has
+                // published its partial of l - 2).  Thread 0 also writes the
+                // later partials, so the stores reach each slot in order.
+                if (tid == 0)
+                    for (int x = l; x < nl0; ++x)
+                        st_bits(part_bits + (size_t)(x & (kPartSlots - 1)) * nwg + wg, kSlotEmpty);
                 res_next_step<BS>(S, io, step, iters, nl0, ri, cl, t, D_psi, D_phi,
                                   L_psi0 + (size_t)((unsigned)nl0 % NCOPY) * CPT * n,
                                   L_phi0 + (size_t)((unsigned)nl0 % NCOPY) * CPT * 4 * G, &s_crow[0][0], NP, s_mu,

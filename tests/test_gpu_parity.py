@@ -58,6 +58,10 @@ def _cases():
         "single_cell": (W.multigroup(seed=8, J=1, N=8, G=2, n_regions=1, length=0.5,
                                      speeds=(2.0, 1.0), dt=0.1), 2),
         "N2_J5": (W.homogeneous(J=5, N=2, length=1.0), 2),
+        # the paper's two-group performance problem: delta = 0.91 at dt = 10 s
+        # (scattering ratio near one), delta = 0.23 at dt = 0.1 s
+        "rosa_S8_dt10": (W.rosa(J=50, N=8, dt=10.0), 2),
+        "rosa_S16_dt0.1": (W.rosa(J=200, N=16, dt=0.1), 2),
     }
 
 
@@ -83,7 +87,7 @@ def test_oci_fp64_lockstep(name):
 
 
 @pytest.mark.parametrize("name", ["homogeneous64_n32", "regions512_n64", "multigroup192_n128",
-                                  "G3_n48", "single_cell", "N2_J5"])
+                                  "G3_n48", "single_cell", "N2_J5", "rosa_S8_dt10", "rosa_S16_dt0.1"])
 def test_si_fp64_lockstep(name):
     p, steps = CASES[name]
     K = 5
@@ -108,6 +112,25 @@ def test_oci_refined_converges_to_oracle(name):
     s.close()
     assert all(i["status"] == 0 for i in infos), infos
     assert rel(got, want) <= 1e-10
+
+
+@pytest.mark.parametrize("name,gpu_tol,oracle_tol", [("rosa_S8_dt10", 1e-11, 1e-12),
+                                                    ("rosa_S16_dt0.1", 1e-12, 1e-14)])
+def test_rosa_converged_to_oracle(name, gpu_tol, oracle_tol):
+    """The two-group problem converged on the GPU (FP64 OCI, FP32-refined OCI
+    and SI) against the oracle's converged OCI answer.  At dt = 10 s the flux
+    reaches ~7, so the absolute stopping test cannot go below ~1e-13 in FP64
+    (the oracle stops at 1e-12 there); the errors left are about tol / (1 -
+    rho) absolute, far inside 1e-10 relative."""
+    p, steps = CASES[name]
+    _announce(name, p, f"rosa converged, gpu tol {gpu_tol}, oracle tol {oracle_tol}")
+    want = oracle.Oracle(p).run("oci", steps=steps, tol=oracle_tol)["phi"]
+    for prec, method in ((B.OCI_FP64, "oci"), (B.OCI_FP32_REFINED, "oci"), (B.OCI_FP64, "si")):
+        s = B.Solver(p, precision=prec, tol=gpu_tol)
+        got, infos = s.run(steps=steps, method=method)
+        s.close()
+        assert all(i["status"] == 0 for i in infos), (prec, method, infos)
+        assert rel(got, want) <= 1e-10, (prec, method, rel(got, want))
 
 
 def test_oci_fp64_converged_iteration_counts_match():
@@ -271,6 +294,10 @@ def _multi_step_cases():
         "regions512_n64": dict(CASES["regions512_n64"][0], steps=5),
         "boundary_n64": b,
         "multigroup128_n256": dict(CASES["multigroup128_n256"][0], steps=3),
+        # two-group problem with 5-8 iterations per step: stopping decisions
+        # fall on the iterations right after a turnover
+        "rosa_S8_J114": W.rosa(J=114, N=8, dt=0.1, steps=8),
+        "rosa_S4_J114": W.rosa(J=114, N=4, dt=0.1, steps=8),
     }
 
 
@@ -299,6 +326,29 @@ def test_run_steps_equals_single_steps(name, prec):
     assert ginfo == winfo
     assert np.array_equal(got, want)
     assert np.array_equal(gstate, wstate)
+
+
+@pytest.mark.parametrize("block", ["256", "1024"])
+def test_run_steps_partial_slots_across_turnovers(block, monkeypatch):
+    """Twelve short steps in one launch of the register-resident kernel: the
+    partial-sum slots of the iterations a turnover skips must not hand a
+    value of the previous step to the next one's stopping decision (all
+    workgroups then stop together, every step converges, and the results
+    equal one call per step bit for bit)."""
+    monkeypatch.setenv("OCI_BLOCK", block)
+    p = W.rosa(J=114, N=8, dt=0.1, steps=12)
+    _announce("rosa_S8_J114", p, f"oci_run_steps x12, block {block}")
+    s = B.Solver(p, precision=B.OCI_FP32_REFINED, tol=1e-10)
+    want, winfo = s.run()
+    s.close()
+    s = B.Solver(p, precision=B.OCI_FP32_REFINED, tol=1e-10)
+    cfg = s.config()
+    got, ginfo = s.run_steps()
+    s.close()
+    assert cfg["resident"] and cfg["block"] == int(block), cfg
+    assert all(i["status"] == 0 for i in ginfo), ginfo
+    assert ginfo == winfo
+    assert np.array_equal(got, want)
 
 
 def test_run_steps_lockstep_matches_oracle():
