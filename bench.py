@@ -16,9 +16,15 @@ then the launch-shape autotuner) happens before the timed region and is
 reported separately.
 
 Other workloads: "homogeneous64", "multigroup8192", "multigroup16384" (one
-problem each), and "batch64": the 64 uneven slabs advanced together by the
+problem each), "batch64": the 64 uneven slabs advanced together by the
 batched persistent launch with K graph-captured steps, against the same slabs
-solved one after another in FP64.
+solved one after another in FP64, and "rosa": the two-group, highly
+scattering performance problem of section 3.2 (table rosa_test; L = 100 cm,
+vacuum, Q = 1, zero start) swept over the cell optical thickness delta =
+Sigma_2 dx (the smaller total cross section), S8 / S16 / S32 and
+dt = 10 s / 0.1 s: K converged steps of each configuration timed for
+FP64 OCI, FP32-refined OCI and SI (setup outside the timed region, as in the
+paper's convergence-loop runtimes).
 
 value = cell-solves / s of the FP32-refined path over the timed region, a
 cell-solve being one cell's 4NG system solved once in one iteration.
@@ -362,6 +368,65 @@ def batch_main(a, torch, B):
     print(json.dumps(out), flush=True)
 
 
+ROSA_DELTAS = (10.0, 4.0, 1.0, 0.4, 0.1, 0.04, 0.01)
+ROSA_ORDERS = (8, 16, 32)
+ROSA_DTS = (10.0, 0.1)
+
+
+def rosa_main(a, torch, B):
+    """The delta / quadrature / time-step sweep of the two-group problem."""
+    from paper_2503_00264_amd import workloads as W
+    K = a.steps
+    rows = []
+    cs_ref = 0
+    t_ref = 0.0
+    for dt in ROSA_DTS:
+        for N in ROSA_ORDERS:
+            for delta in ROSA_DELTAS:
+                J = max(1, int(round(W.ROSA_SIGMA_MIN * W.ROSA_LENGTH / delta)))
+                probs = [W.rosa(J=J, N=N, dt=dt, steps=K)]
+                tune = not a.no_autotune
+                r64 = run_method(probs, "oci", B.OCI_FP64, K, a.warmup, a.tol, torch, B, tune)
+                rrf = run_method(probs, "oci", B.OCI_FP32_REFINED, K, a.warmup, a.tol, torch, B, tune)
+                rsi = run_method(probs, "si", B.OCI_FP64, K, a.warmup, a.tol, torch, B, False)
+                torch.cuda.empty_cache()
+                cs_ref += rrf["cell_solves"]
+                t_ref += rrf["time_s"]
+                row = {"dt": dt, "N": N, "n": 8 * N, "delta": round(W.ROSA_SIGMA_MIN * W.ROSA_LENGTH / J, 5),
+                       "J": J, "oci_fp64_s": round(r64["time_s"], 6), "oci_refined_s": round(rrf["time_s"], 6),
+                       "si_s": round(rsi["time_s"], 6),
+                       "oci_iterations_per_step": r64["per"][0]["iterations_per_step"],
+                       "si_iterations_per_step": rsi["per"][0]["iterations_per_step"],
+                       "speedup_fp64_oci_over_si": round(rsi["time_s"] / r64["time_s"], 3),
+                       "speedup_refined_oci_over_si": round(rsi["time_s"] / rrf["time_s"], 3),
+                       "status": sorted(set(r64["status"]) | set(rrf["status"]) | set(rsi["status"]))}
+                rows.append(row)
+                print(f"[rosa] dt={dt} S{N} delta={row['delta']} J={J}: OCI fp64 {row['oci_fp64_s'] * 1e3:.2f} ms "
+                      f"refined {row['oci_refined_s'] * 1e3:.2f} ms SI {row['si_s'] * 1e3:.2f} ms "
+                      f"({row['oci_iterations_per_step']:.0f} / {row['si_iterations_per_step']:.0f} iterations)",
+                      file=sys.stderr, flush=True)
+    best = {}
+    for dt in ROSA_DTS:
+        for N in ROSA_ORDERS:
+            sel = [r for r in rows if r["dt"] == dt and r["N"] == N]
+            top = max(sel, key=lambda r: r["speedup_fp64_oci_over_si"])
+            best[f"dt={dt} S{N}"] = {"delta": top["delta"], "speedup_fp64_oci_over_si": top["speedup_fp64_oci_over_si"]}
+    out = {
+        "metric": "convergence-loop seconds over the delta sweep: FP64 OCI, FP32-refined OCI and SI @tol",
+        "value": round(cs_ref / max(t_ref, 1e-12), 1), "unit": "cell-solves/s", "n_gpus": 1, "steps": K,
+        "warmup": a.warmup, "ms_per_step": round(t_ref * 1e3 / K, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (OCI, SI); f32 solve + f64 residual (refined)",
+        "data": "synthetic (the paper's two-group material table; no external data)",
+        "config": {"workload": f"rosa: two groups, L = 100 cm, S_N in {list(ROSA_ORDERS)}, "
+                               f"delta = Sigma_2 dx in {list(ROSA_DELTAS)}, dt in {list(ROSA_DTS)} s, "
+                               f"{K} steps each, tol {a.tol}", "tol": a.tol},
+        "roofline": None,
+        "sweep": rows,
+        "best_delta": best,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -372,6 +437,9 @@ def main():
     torch.cuda.set_device(0)
     if a.workload == "batch64":
         batch_main(a, torch, B)
+        return
+    if a.workload == "rosa":
+        rosa_main(a, torch, B)
         return
     base, probs = problems(a.workload)
     N, G, J = base["N"], base["G"], base["J"]

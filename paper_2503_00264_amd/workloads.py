@@ -166,7 +166,13 @@ def batch(seed=5, n_slabs=64, j_range=(256, 8192), n_choices=(8, 16, 32),
     return slabs
 
 
-def rosa(J=1000, N=8, length=100.0, dt=0.1, steps=1):
+# The smaller of the two total cross sections (group 2), 1/cm: the paper
+# states the cell optical thickness delta of this problem with it.
+ROSA_SIGMA_MIN = 0.45468
+ROSA_LENGTH = 100.0
+
+
+def rosa(J=1000, N=8, length=ROSA_LENGTH, dt=0.1, steps=1):
     """The paper's two-group test problem (Table 2), vacuum, Q=1, zero start."""
     st = np.array([1.5454, 0.45468])
     # [g][gp] = gp -> g : within-group 0.61789 / 0.0072534, 1->2 0.92747, 2->1 0.38211
