@@ -184,6 +184,17 @@ def rosa(J=1000, N=8, length=ROSA_LENGTH, dt=0.1, steps=1):
                     np.array([1.0, 0.5]), dt, steps, qq, N)
 
 
+def fourier_verification(seed=2025, J=1000, N=8):
+    """The paper's Fourier verification problem (section 3.1): 100 cm, vacuum,
+    Sigma = 2.5/cm, dx = 0.1 cm, c = 0.9, dt = 0.1 s, v = 4 (read as cm/s,
+    which gives the stated tau = 1), no source, S8, and a uniform [0, 1]
+    random start for the angular flux."""
+    p = homogeneous(J=J, N=N, length=0.1 * J, sigma_t=2.5, c=0.9, speed=4.0, dt=0.1, steps=1,
+                    q=0.0)
+    p["psi_init"] = np.random.default_rng(seed).uniform(0.0, 1.0, size=(J, 1, N, 2))
+    return p
+
+
 CONFIG_NAMES = ("homogeneous64", "regions4096", "multigroup8192",
                 "multigroup16384", "batch64")
 

@@ -133,6 +133,32 @@ def test_rosa_converged_to_oracle(name, gpu_tol, oracle_tol):
         assert rel(got, want) <= 1e-10, (prec, method, rel(got, want))
 
 
+def test_e_history_on_fourier_verification_problem():
+    """e_l and rho_e after k iterations (fixed_iters = k) of FP64 OCI on the
+    paper's verification problem (1000 cells, random start) equal the
+    oracle's iteration history: the GPU's per-iteration convergence record
+    is the one the empirical spectral-radius trace reads."""
+    p = W.fourier_verification()
+    _announce("fourier_verification", p, "e_l history, fp64 OCI, k in 2..40")
+    o = oracle.Oracle(p, methods=("oci",))
+    pp, pi = o.initial_state(p["psi_init"])
+    phi, oinfo = o.step("oci", pp, pi, q=p["q"], fixed_iters=40, history=True)
+    e = oinfo["e_hist"]
+    # e_l is a norm of differences of fluxes that stay O(max|phi|): both sides
+    # agree to its absolute rounding scale, 1e-14 max|phi| sqrt(entries)
+    floor = 1e-14 * np.abs(phi).max() * np.sqrt(phi.size)
+    for k in (2, 5, 10, 20, 40):
+        s = B.Solver(p, precision=B.OCI_FP64, fixed_iters=k)
+        _, infos = s.run(steps=1)
+        s.close()
+        i = infos[0]
+        tol_k, tol_k1 = 1e-12 * e[k - 1] + floor, 1e-12 * e[k - 2] + floor
+        assert i["iterations"] == k and i["status"] == 0, i
+        assert abs(i["e_last"] - e[k - 1]) <= tol_k, (k, i["e_last"], e[k - 1])
+        rho = e[k - 1] / e[k - 2]
+        assert abs(i["rho_e"] - rho) <= rho * (tol_k / e[k - 1] + tol_k1 / e[k - 2]), (k, i["rho_e"], rho)
+
+
 def test_oci_fp64_converged_iteration_counts_match():
     p = W.config("homogeneous64")
     _announce("homogeneous64", p, "converged, 10 steps, tol 1e-10")
