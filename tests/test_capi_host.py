@@ -100,6 +100,8 @@ def test_step_calls_reject_null_handle_and_outputs():
     L = B.lib()
     assert L.oci_step(None, None, None, None, None, None, None) == B.OCI_ERR_INVALID
     assert L.si_step(None, None, None, None, None, None, None) == B.OCI_ERR_INVALID
+    assert L.oci_run_steps(None, 3, None, None, None, None, None, None) == B.OCI_ERR_INVALID
+    assert L.oci_run_steps(None, 0, None, None, None, None, None, None) == B.OCI_ERR_INVALID
     assert L.oci_set_state(None, None) == B.OCI_ERR_INVALID
     assert L.oci_get_state(None, None) == B.OCI_ERR_INVALID
     assert L.oci_destroy(None) == B.OCI_ERR_INVALID
