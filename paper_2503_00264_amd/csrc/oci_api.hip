@@ -225,7 +225,7 @@ static int configure(oci_handle *h, int block, bool allow_local, bool allow_res,
     long nwg = 0;
     size_t dyn_lds = 0;
     // dynamic LDS of the local kernel: cells x (n + 4G) (kResidentCopies
-    // times with resident rows) + tiles x 2NG doubles
+    // times with resident rows) + tiles x 2NG doubles (+ the flux scratch)
     auto try_local = [&](bool r) -> bool {
         size_t stat = 0;
         if (local_static_lds(h->fp32, h->np, r, block, &stat) != hipSuccess) return false;
@@ -236,8 +236,12 @@ static int configure(oci_handle *h, int block, bool allow_local, bool allow_res,
         if (w > wg_cap) w = wg_cap;
         for (int it = 0; it < 8 && w >= 1; ++it) {
             const long tpw = (ntiles + w - 1) / w;
-            // resident rows keep kResidentCopies copies of the range's Psi and phi
-            const size_t dyn = ((size_t)(r ? kResidentCopies : 1) * tpw * cpt * (h->n + 4 * G) + (size_t)tpw * 2 * N * G) * 8;
+            // resident rows keep kResidentCopies copies of the range's Psi and
+            // phi; streamed rows sum phi through LDS ([cells per tile][np])
+            // unless N is a power of two up to 16 with one row per thread
+            const bool wx = !r && !(rpt == 1 && (N & (N - 1)) == 0 && N <= 16);
+            const size_t dyn = ((size_t)(r ? kResidentCopies : 1) * tpw * cpt * (h->n + 4 * G) + (size_t)tpw * 2 * N * G +
+                                (wx ? (size_t)cpt * h->np : 0)) * 8;
             if (stat + dyn > lds_max) return false;
             int o = 0;
             if (local_occupancy(h->fp32, h->np, r, block, dyn, &o) != hipSuccess || o < 1) return false;

@@ -723,7 +723,6 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
 
     extern __shared__ __align__(16) double s_dyn[];
     __shared__ __align__(16) T s_vec[CPT][NP];
-    __shared__ double s_wx[CPT][NP];
     __shared__ double s_mu[NP / 4], s_w[NP / 4];
     __shared__ double s_max[BS / 64];
     __shared__ double s_part[2][BS / 64];   // per-wave partial sums, by iteration parity
@@ -743,6 +742,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     double *L_psi = s_dyn;                                   // [ncell][n]
     double *L_phi = L_psi + (size_t)ncell * n;               // [ncell][4G]
     double *L_snap = L_phi + (size_t)ncell * 4 * G;          // [ntw][2][NG]: R-going, L-going
+    double *L_wx = L_snap + (size_t)ntw * 2 * NG;            // [CPT][NP] w_m psi, only without tree_phi
     // exchange buffer [2 parity][nwg][2 side][2 lev][G][nh] slots of two
     // words; side 0: my first cell's L corners of mu<0 angles, side 1: my
     // last cell's R corners of mu>0
@@ -769,7 +769,10 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     }
     __syncthreads();
 
-    const bool tree_phi = WAVE_CELL && (N & (N - 1)) == 0;
+    // phi by lane moves within the wave: the N angles of a (g, u) pair lie in
+    // 4N consecutive rows, a power of two that divides 64, so they share a
+    // wave even when the cell spans several
+    const bool tree_phi = RPT == 1 && (N & (N - 1)) == 0 && N <= 16;
     uint64_t *part_bits = reinterpret_cast<uint64_t *>(S.partials);
     double e_prev = __builtin_nan("");
     uint64_t pv[PV];   // the decision wave's partial sums, loaded at the end of the previous iteration
@@ -1020,20 +1023,20 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
                     const int i = t + r * TPC;
-                    s_wx[cl][i] = (i < n ? s_w[(i >> 2) % N] : 0.0) * xs[r];
+                    L_wx[cl * NP + i] = (i < n ? s_w[(i >> 2) % N] : 0.0) * xs[r];
                 }
                 __syncthreads();
                 if (live && t < 4 * G) {
                     const int g = t >> 2, u = t & 3;
                     double f = 0.0;
-                    for (int m = 0; m < N; ++m) f += s_wx[cl][(g * N + m) * 4 + u];
+                    for (int m = 0; m < N; ++m) f += L_wx[cl * NP + (g * N + m) * 4 + u];
                     const double f0 = Lf[t];
                     Lf[t] = f;
                     if (S.norm == 0) dsq += (f - f0) * (f - f0);
                 }
             }
             dsq_acc += dsq;
-            if (tile + 1 < tile1) __syncthreads();   // s_vec / s_wx are reused by the next tile
+            if (tile + 1 < tile1) __syncthreads();   // s_vec / L_wx are reused by the next tile
         }
 
         // (5) the partial of iteration l (the edges just published need not
