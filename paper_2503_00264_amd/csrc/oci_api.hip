@@ -225,7 +225,8 @@ static int configure(oci_handle *h, int block, bool allow_local, bool allow_res,
     long nwg = 0;
     size_t dyn_lds = 0;
     // dynamic LDS of the local kernel: cells x (n + 4G) (kResidentCopies
-    // times with resident rows) + tiles x 2NG doubles (+ the flux scratch)
+    // times with resident rows) + internal tile boundaries x 2NG doubles
+    // (+ the flux scratch)
     auto try_local = [&](bool r) -> bool {
         size_t stat = 0;
         if (local_static_lds(h->fp32, h->np, r, block, &stat) != hipSuccess) return false;
@@ -240,8 +241,8 @@ static int configure(oci_handle *h, int block, bool allow_local, bool allow_res,
             // phi; streamed rows sum phi through LDS ([cells per tile][np])
             // unless N is a power of two up to 16 with one row per thread
             const bool wx = !r && !(rpt == 1 && (N & (N - 1)) == 0 && N <= 16);
-            const size_t dyn = ((size_t)(r ? kResidentCopies : 1) * tpw * cpt * (h->n + 4 * G) + (size_t)tpw * 2 * N * G +
-                                (wx ? (size_t)cpt * h->np : 0)) * 8;
+            const size_t dyn = ((size_t)(r ? kResidentCopies : 1) * tpw * cpt * (h->n + 4 * G) +
+                                (size_t)(r ? tpw : tpw - 1) * 2 * N * G + (wx ? (size_t)cpt * h->np : 0)) * 8;
             if (stat + dyn > lds_max) return false;
             int o = 0;
             if (local_occupancy(h->fp32, h->np, r, block, dyn, &o) != hipSuccess || o < 1) return false;

@@ -723,7 +723,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
 
     extern __shared__ __align__(16) double s_dyn[];
     __shared__ __align__(16) T s_vec[CPT][NP];
-    __shared__ double s_mu[NP / 4], s_w[NP / 4];
+    __shared__ double s_w[NP / 4];
     __shared__ double s_max[BS / 64];
     __shared__ double s_part[2][BS / 64];   // per-wave partial sums, by iteration parity
     __shared__ double s_dec[2][4];          // decision (done, status, e, rho), by iteration parity
@@ -741,8 +741,8 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
     const int ncell = ntw * CPT;
     double *L_psi = s_dyn;                                   // [ncell][n]
     double *L_phi = L_psi + (size_t)ncell * n;               // [ncell][4G]
-    double *L_snap = L_phi + (size_t)ncell * 4 * G;          // [ntw][2][NG]: R-going, L-going
-    double *L_wx = L_snap + (size_t)ntw * 2 * NG;            // [CPT][NP] w_m psi, only without tree_phi
+    double *L_snap = L_phi + (size_t)ncell * 4 * G;          // [ntw - 1][2][NG]: R-going, L-going
+    double *L_wx = L_snap + (size_t)(ntw > 1 ? ntw - 1 : 0) * 2 * NG;   // [CPT][NP] w_m psi, only without tree_phi
     // exchange buffer [2 parity][nwg][2 side][2 lev][G][nh] slots of two
     // words; side 0: my first cell's L corners of mu<0 angles, side 1: my
     // last cell's R corners of mu>0
@@ -751,7 +751,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
         return exch_bits + 2 * ((((size_t)par * nwg + w) * 2 + side) * NG + ((size_t)lev * G + g) * nh + mm);
     };
 
-    for (int m = tid; m < N; m += BS) { s_mu[m] = S.mu[m]; s_w[m] = S.w[m]; }
+    for (int m = tid; m < N; m += BS) s_w[m] = S.w[m];
 
     const T *Xall = reinterpret_cast<const T *>(S.X);
     // the iterate and its scalar flux into LDS
@@ -843,14 +843,14 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
         // edges crossing internal tile boundaries, before any tile updates
         if (ntw > 1) {
             for (int k = tid_o; k < (ntw - 1) * 2 * NG; k += BS) {
-                const int tt = 1 + k / (2 * NG), r = k % (2 * NG);
+                const int tt = 1 + k / (2 * NG), r = k % (2 * NG);   // the boundary before tile tt
                 const int side = r / NG, q = r % NG;           // side 0: R-going, 1: L-going
                 const int lev = q / (G * nh), g = (q / nh) % G, mm = q % nh;
                 const int jb = (tile0 + tt) * CPT;             // first cell of tile tt
                 double v;
                 if (side == 0) v = L_psi[(size_t)(jb - 1 - c0) * n + (g * N + nh + mm) * 4 + 2 * lev + 1];
                 else v = L_psi[(size_t)(jb - c0) * n + (g * N + mm) * 4 + 2 * lev];
-                L_snap[(size_t)tt * 2 * NG + r] = v;
+                L_snap[(size_t)(tt - 1) * 2 * NG + r] = v;
             }
             __syncthreads();
         }
@@ -872,7 +872,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                 xold[r] = 0.0;
                 if (live && i < n) {
                     const int g = i / (4 * N), m = (i >> 2) % N, u = i & 3;
-                    const double mu = s_mu[m];
+                    const double mu = S.mu[m];
                     xold[r] = Lp[i];
                     b = S.crhs[(size_t)j * n + i];
                     const int lev = u >> 1;
@@ -883,7 +883,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                         else if (j % CPT != 0)
                             e = Lp[i - n + 1];                                   // same tile
                         else if (j - 1 >= c0)
-                            e = L_snap[(size_t)tt * 2 * NG + (lev * G + g) * nh + (m - nh)];
+                            e = L_snap[(size_t)(tt - 1) * 2 * NG + (lev * G + g) * nh + (m - nh)];
                         else if (l == 0)
                             e = psi_g[(size_t)(j - 1) * n + i + 1];
                         else
@@ -896,7 +896,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                         else if ((j + 1) % CPT != 0)
                             e = Lp[i + n - 1];                                   // same tile
                         else if (j + 1 < c1)
-                            e = L_snap[(size_t)(tt + 1) * 2 * NG + NG + (lev * G + g) * nh + m];
+                            e = L_snap[(size_t)tt * 2 * NG + NG + (lev * G + g) * nh + m];
                         else if (l == 0)
                             e = psi_g[(size_t)(j + 1) * n + i - 1];
                         else
@@ -918,7 +918,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                     if (live && i < n) {
                         const int g = i / (4 * N), u = i & 3;
                         double cf[4];
-                        lc_row(S, j, g, s_mu[(i >> 2) % N], u, cf);
+                        lc_row(S, j, g, S.mu[(i >> 2) % N], u, cf);
                         const double *p = Lp + (i & ~3);
                         const double lp4 = cf[0] * p[0] + cf[1] * p[1] + cf[2] * p[2] + cf[3] * p[3];
                         double sc = 0.0;
