@@ -194,7 +194,7 @@ def setup_model(probs, setup_s, fp32):
                 note="wall time of oci_setup (host uploads and synchronisation included)")
 
 
-def roofline_for(prim, probs, fp32):
+def roofline_for(prim, probs, fp32, workload=None):
     """Roofline of the dominant kernel (the persistent OCI kernel of the
     measured path: one launch per problem for all K steps when its rows are
     register-resident, one per time step otherwise).
@@ -222,8 +222,15 @@ def roofline_for(prim, probs, fp32):
     gbs = bpc * cpl / avg_launch_s / 1e9
     tflops = fpc * cpl / avg_launch_s / 1e12
     label = kernel_label(prim["configs"][0], fp32, np_)
-    tr = recorded_traffic(label)
-    traffic = None if tr is None else round(tr * cpl, 1)
+    if prim["configs"][0].get("resident"):
+        tr = recorded_traffic(label)
+        traffic = None if tr is None else round(tr * cpl, 1)
+    else:
+        # streamed rows: the counters' HBM bytes per algorithmic byte for this
+        # kernel on this workload, if a summary for it is committed
+        name = label.split("<")[0]
+        ratio = recorded_traffic(label, f"{name}_{workload}.md", "HBM bytes per algorithmic byte") if workload else None
+        traffic = None if ratio is None else round(ratio * bpc * cpl, 1)
     common = dict(kernel=label, avg_launch_us=round(avg_launch_s * 1e6, 2),
                   cell_iterations_per_launch=round(cpl, 1), bytes_per_cell_iteration=bpc,
                   flops_per_cell_iteration=fpc)
@@ -468,14 +475,14 @@ def main():
         "config": {"workload": f"{a.workload}: J={J} N={N} G={G} n={n}, dt {keys}, tol {a.tol}, "
                                f"one step = one converged time step of each dt",
                    "J": J, "N": N, "G": G, "n": n, "dts": [p["dt"] for p in probs], "tol": a.tol},
-        "roofline": roofline_for(prim, probs, True),
+        "roofline": roofline_for(prim, probs, True, a.workload),
         "comparison": {"fp32_refined": summary(prim, "FP32 LU+inverse, FP64 residual refinement", a.steps, keys)},
     }
     labels = {"fp64": "FP64 LU+inverse OCI", "si": "FP64 source iteration sweep"}
     for k, r in comp.items():
         out["comparison"][k] = summary(r, labels[k], a.steps, keys)
     if "fp64" in comp:
-        out["comparison"]["fp64"]["roofline"] = roofline_for(comp["fp64"], probs, False)
+        out["comparison"]["fp64"]["roofline"] = roofline_for(comp["fp64"], probs, False, a.workload)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs[0], a.cpu_seconds)
     print(json.dumps(out), flush=True)
