@@ -55,6 +55,15 @@
  *   asynchronously.  A handle is not thread-safe; one handle must not be used
  *   from two streams at once.
  *
+ * Co-residency: the iteration loop of a step is one persistent launch whose
+ *   workgroups wait on each other (edge hand-offs, partial sums, barriers).
+ *   The launch is sized so that all its workgroups fit on the device at once,
+ *   which holds only while nothing else occupies the compute units: a step
+ *   must not overlap other kernels on the same device (another handle's step
+ *   on a second stream, other work of the caller, another process).  Every
+ *   wait is bounded; if a workgroup could not be scheduled the waits expire,
+ *   the step stops and its info reports OCI_ERR_DEVICE.  A step never hangs.
+ *
  * Errors: every call returns an oci_status; negative values are errors and
  * leave the handle usable unless stated.  Arguments are validated on the host
  * before anything is launched.
@@ -77,12 +86,49 @@ typedef enum {
     OCI_ERR_HIP = -2,          /* a HIP runtime call failed */
     OCI_ERR_SINGULAR = -3,     /* a cell matrix has a zero pivot */
     OCI_ERR_WORKSPACE = -4,    /* workspace NULL, too small or misaligned */
-    OCI_ERR_UNSUPPORTED = -5,  /* shape beyond the compiled kernels (4NG > 512) */
-    OCI_ERR_DEVICE = -6        /* a device-side guard tripped (barrier spin limit) */
+    OCI_ERR_UNSUPPORTED = -5,  /* shape or option beyond the compiled kernels (4NG > 512;
+                                  the structured solve with FP32, the angular norm or
+                                  G > 8; red-black or periodic without it) */
+    OCI_ERR_DEVICE = -6        /* a device-side wait expired (a workgroup of the
+                                  persistent launch was not co-resident) */
 } oci_status;
 
 typedef enum { OCI_FP64 = 0, OCI_FP32_REFINED = 1 } oci_precision;
 typedef enum { OCI_NORM_SCALAR = 0, OCI_NORM_ANGULAR = 1 } oci_norm;
+
+/* How a cell system is solved in each OCI iteration.
+ *   OCI_SOLVE_DENSE       the factored (4NG)^2 matrix, kept as its inverse
+ *                         (the paper's stored-LHS design, section 2.5).
+ *   OCI_SOLVE_STRUCTURED  the same exact solve through the structure of A_j
+ *                         (section 2.4: block diagonal 4x4 corner blocks minus
+ *                         a scattering coupling of rank 4G): the corner blocks
+ *                         are inverted in closed form and the coupling through
+ *                         a 4G x 4G capacitance matrix inverted once per cell
+ *                         at setup.  FP64 only (precision OCI_FP64), scalar
+ *                         norm only, G <= 8; no n x n factors are stored.  SI
+ *                         is available on the same handle. */
+typedef enum { OCI_SOLVE_DENSE = 0, OCI_SOLVE_STRUCTURED = 1 } oci_solver;
+
+/* Order in which the cells of one OCI iteration are solved.
+ *   OCI_ORDER_JACOBI     every cell from the previous iterate (cell-wise block
+ *                        Jacobi, eq. oci; the paper's OCI).
+ *   OCI_ORDER_RED_BLACK  the even cells from the previous iterate, then the
+ *                        odd cells from the even cells' new values (the block
+ *                        Gauss-Seidel ordering the paper's introduction names
+ *                        as the alternative); the same fixed point, the
+ *                        iteration operator's spectral radius squared.  One
+ *                        iteration still solves every cell once.  Structured
+ *                        solve only. */
+typedef enum { OCI_ORDER_JACOBI = 0, OCI_ORDER_RED_BLACK = 1 } oci_ordering;
+
+/* Boundary of the slab.
+ *   OCI_BOUNDARY_INCIDENT  prescribed incident fluxes (vacuum when NULL).
+ *   OCI_BOUNDARY_PERIODIC  a periodic mesh: cell 0 and cell J - 1 are
+ *                          neighbours (the setting of the paper's Fourier
+ *                          analysis, section 2.3, and of its verification
+ *                          runs); incident-flux arguments are ignored.
+ *                          Structured solve only. */
+typedef enum { OCI_BOUNDARY_INCIDENT = 0, OCI_BOUNDARY_PERIODIC = 1 } oci_boundary;
 
 /* Problem description.  Host pointers, read during oci_setup only. */
 typedef struct {
@@ -100,6 +146,9 @@ typedef struct {
                                  with no stopping test (lock-step comparisons) */
     int32_t precision;        /* oci_precision */
     int32_t norm;             /* oci_norm, OCI only */
+    int32_t solver;           /* oci_solver (0 = dense) */
+    int32_t ordering;         /* oci_ordering (0 = Jacobi) */
+    int32_t boundary;         /* oci_boundary (0 = incident fluxes) */
 } oci_desc;
 
 /* Per-step result, written to device memory by oci_step / si_step. */
@@ -149,22 +198,49 @@ int oci_step(oci_handle *h, const double *q_dev, const double *inc_left_dev,
              const double *inc_right_dev, double *phi_out_dev, double *psi_out_dev,
              oci_step_info *info_dev);
 
-/* nsteps consecutive OCI time steps with the same sources and incident
- * fluxes (time-independent Q and boundary data, as in the test problem of the
- * paper's GPU performance study, section 3.2, table rosa_test); the same
- * result, step for step, as nsteps calls of oci_step.
- *   phi_out_dev   [nsteps][J][G][4] scalar flux of each step's last iterate
- *   psi_out_dev   [J][G][N][4] angular flux of the last step's last iterate,
- *                 NULL = skip
- *   info_dev      nsteps oci_step_info records in device memory
+/* nsteps consecutive OCI time steps (Algorithm 2 repeated over the steps
+ * of section 2.1's time discretisation); the same result, step for step, as
+ * nsteps calls of oci_step with each step's sources.
+ *   q_dev, q_stride      step k's Q is q_dev + k q_stride ([J][G][4] each;
+ *                        q_stride = 0: the same Q every step, as in the test
+ *                        problem of the paper's GPU performance study,
+ *                        section 3.2, table rosa_test); q_dev NULL = none
+ *   inc_left_dev, inc_right_dev, inc_stride
+ *                        step k's incident fluxes are inc_*_dev + k inc_stride
+ *                        ([2][G][N/2] each; 0: the same every step); NULL =
+ *                        vacuum
+ *   phi_out_dev          [nsteps][J][G][4] scalar flux of each step's last
+ *                        iterate
+ *   psi_out_dev          [J][G][N][4] angular flux of the last step's last
+ *                        iterate, NULL = skip
+ *   info_dev             nsteps oci_step_info records in device memory
  * With the register-resident kernel (see oci_get_config) the steps run in one
  * launch: each step's stop turns the iterate over to the next step inside the
  * kernel, so the inverse rows are loaded once for all of them.  Otherwise it
- * calls oci_step nsteps times.  OCI_ERR_INVALID if nsteps < 1 or an output is
- * NULL. */
-int oci_run_steps(oci_handle *h, int32_t nsteps, const double *q_dev, const double *inc_left_dev,
-                  const double *inc_right_dev, double *phi_out_dev, double *psi_out_dev,
-                  oci_step_info *info_dev);
+ * calls oci_step nsteps times.  OCI_ERR_INVALID if nsteps < 1, a stride is
+ * negative or an output is NULL. */
+int oci_run_steps(oci_handle *h, int32_t nsteps, const double *q_dev, int64_t q_stride,
+                  const double *inc_left_dev, const double *inc_right_dev, int64_t inc_stride,
+                  double *phi_out_dev, double *psi_out_dev, oci_step_info *info_dev);
+
+/* Capture n_steps OCI time steps into a HIP graph held by the handle (its
+ * stream must not be NULL), with per-step arguments for time-dependent
+ * sources Q_k, Q_{k+1/2} and incident fluxes psi_inc(t) (section 2.1):
+ * host arrays of n_steps device pointers (q_dev, inc_left_dev, inc_right_dev,
+ * psi_out_dev: arrays or entries may be NULL, as in oci_step; phi_out_dev:
+ * every entry required) and info_dev, n_steps oci_step_info in device
+ * memory.  Nothing runs until oci_replay_steps.  The steps' kernels are those
+ * of oci_step; the first iterate of each step is decided on the device (the
+ * state after oci_set_state, else the last iterate), so a replay equals
+ * n_steps oci_step calls bit for bit.  A new capture replaces the graph;
+ * oci_destroy releases it. */
+int oci_capture_steps(oci_handle *h, int32_t n_steps, const double *const *q_dev,
+                      const double *const *inc_left_dev, const double *const *inc_right_dev,
+                      double *const *phi_out_dev, double *const *psi_out_dev, oci_step_info *info_dev);
+
+/* Launch the captured steps on the handle's stream (asynchronous);
+ * OCI_ERR_INVALID if nothing was captured. */
+int oci_replay_steps(oci_handle *h);
 
 /* One source-iteration time step (Appendix A, Algorithm 1) on the same state
  * and with the same arguments as oci_step. */
@@ -194,6 +270,14 @@ int oci_profile_read(oci_handle *h, double *ms, int32_t *steps);
  * state is zero afterwards (call it right after oci_setup).  config, if not
  * NULL, receives the chosen shape as oci_get_config reports it. */
 int oci_autotune(oci_handle *h, int32_t iters, int32_t *config);
+
+/* Per-iteration record of the stopping quantity (instrumentation for the
+ * convergence studies of section 3.1): with e_hist_dev non-NULL, every later
+ * OCI step writes e_l of its iteration l (l = 1, 2, ...) into
+ * e_hist_dev[l - 1] for l <= capacity (device memory, owned by the caller;
+ * entries beyond the step's iteration count keep their old contents; a
+ * multi-step launch leaves the last step's record).  NULL turns it off. */
+int oci_set_history(oci_handle *h, double *e_hist_dev, int32_t capacity);
 
 /* Current launch shape: config[6] = {threads per workgroup, local kernel (0/1),
  * register-resident rows (0/1), barrier group size, workgroups, tiles}. */
@@ -232,12 +316,28 @@ int oci_batch_bind(oci_batch *b, const double *const *q_dev, const double *const
                    const double *const *inc_right_dev, double *const *phi_out_dev,
                    oci_step_info *info_dev);
 
-/* One time step of every slab (asynchronous; results in the bound outputs). */
+/* Bind n_steps argument sets (1 <= n_steps <= 64), one per time step, for
+ * time-dependent sources and incident fluxes (the Q_k, Q_{k+1/2} and
+ * psi_inc(t) of section 2.1): host arrays of n_steps x nslab device pointers,
+ * entry [i][k] for step i of slab k (q, incident fluxes: entries or whole
+ * arrays may be NULL; phi_out: every entry required), and info_dev,
+ * n_steps x nslab oci_step_info in device memory.  Eager steps use the sets
+ * in order, cyclically; a capture of n steps records the next n sets.
+ * oci_batch_bind is the one-set case.  Discards a captured graph, uploads
+ * the launch tables and synchronises the stream. */
+int oci_batch_bind_steps(oci_batch *b, int32_t n_steps, const double *const *q_dev,
+                         const double *const *inc_left_dev, const double *const *inc_right_dev,
+                         double *const *phi_out_dev, oci_step_info *info_dev);
+
+/* One time step of every slab with the next bound argument set
+ * (asynchronous; results in that set's outputs). */
 int oci_batch_step(oci_batch *b);
 
 /* Capture n_steps batched steps into a HIP graph held by the batch (needs a
- * non-null stream), and launch it.  Replays continue from the current state;
- * the bound outputs hold the last step's results. */
+ * non-null stream) and instantiate it; nothing runs until the first
+ * oci_batch_replay.  Step i of the graph uses the bound argument set
+ * (next + i) mod n_bound, next being the set the next eager step would use.
+ * Each replay runs the n_steps steps from the current state. */
 int oci_batch_capture(oci_batch *b, int32_t n_steps);
 int oci_batch_replay(oci_batch *b);
 
@@ -246,9 +346,10 @@ int oci_batch_set_state(oci_batch *b, int32_t k, const double *psi_prev_dev);
 int oci_batch_get_state(const oci_batch *b, int32_t k, double *psi_prev_dev);
 
 /* Batch autotuning: re-size every slab's block of workgroups in proportion
- * to J x (4NG)^2 x (iterations of its last step, read from the bound info
- * array), so slabs that converge slowly get more of the launch.  Synchronises
- * the stream; a captured graph is discarded (capture again afterwards). */
+ * to J x (4NG)^2 x (iterations of the last step enqueued, read from its
+ * argument set's info records), so slabs that converge slowly get more of
+ * the launch.  OCI_ERR_INVALID before any step.  Synchronises the stream; a
+ * captured graph is discarded (capture again afterwards). */
 int oci_batch_rebalance(oci_batch *b);
 
 /* Launch geometry: total workgroups and, if nwg_per_slab is not NULL, the

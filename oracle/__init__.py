@@ -21,6 +21,7 @@ _LIB = os.path.join(_HERE, "liboci_oracle.so")
 
 OK, NOT_CONVERGED, NONFINITE, ERR_INVALID, ERR_SINGULAR = 0, 1, 2, -1, -3
 NORM_SCALAR, NORM_ANGULAR = 0, 1
+ORDER_JACOBI, ORDER_RED_BLACK = 0, 1
 
 
 def build(openmp: bool = True) -> str:
@@ -43,7 +44,7 @@ class _Problem(C.Structure):
 
 class _Control(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int),
-                ("fixed_iters", C.c_int), ("norm", C.c_int)]
+                ("fixed_iters", C.c_int), ("norm", C.c_int), ("ordering", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -101,6 +102,7 @@ def _load(path):
     L.orc_lu_solve.restype = None
     L.orc_oci_setup.argtypes = [P, vp, vp]
     L.orc_oci_iterate.argtypes = [P] + [vp] * 9
+    L.orc_oci_iterate_rb.argtypes = [P] + [vp] * 9
     L.orc_oci_step.argtypes = [P, Ctl] + [vp] * 9 + [Inf, vp]
     L.orc_si_setup.argtypes = [P, vp, vp]
     L.orc_si_sweep.argtypes = [P] + [vp] * 9
@@ -178,11 +180,13 @@ class Oracle:
         psi_iter = np.concatenate([psi_prev, psi_prev], axis=-1).copy()
         return psi_prev, psi_iter
 
-    def oci_iterate(self, psi_in, psi_prev, q=None, q_ang=None, inc_l=None, inc_r=None):
+    def oci_iterate(self, psi_in, psi_prev, q=None, q_ang=None, inc_l=None, inc_r=None,
+                    ordering=ORDER_JACOBI):
         psi_in = _f64(psi_in)
         out = np.empty_like(psi_in)
         q, q_ang, inc_l, inc_r, psi_prev = map(_f64, (q, q_ang, inc_l, inc_r, psi_prev))
-        lib().orc_oci_iterate(C.byref(self.cp), _ptr(self.lu), _ptr(self.piv), _ptr(q),
+        fn = lib().orc_oci_iterate_rb if ordering == ORDER_RED_BLACK else lib().orc_oci_iterate
+        fn(C.byref(self.cp), _ptr(self.lu), _ptr(self.piv), _ptr(q),
                               _ptr(q_ang), _ptr(psi_prev), _ptr(inc_l), _ptr(inc_r),
                               _ptr(psi_in), _ptr(out))
         return out
@@ -198,11 +202,11 @@ class Oracle:
 
     def step(self, method, psi_prev, psi_iter, q=None, q_ang=None, inc_l=None,
              inc_r=None, tol=1e-10, max_iters=100000, fixed_iters=0,
-             norm=NORM_SCALAR, history=False):
+             norm=NORM_SCALAR, history=False, ordering=ORDER_JACOBI):
         """One time step in place on (psi_prev, psi_iter); returns (phi, info dict)."""
         assert psi_prev.flags.c_contiguous and psi_prev.dtype == np.float64
         assert psi_iter.flags.c_contiguous and psi_iter.dtype == np.float64
-        ctl = _Control(float(tol), int(max_iters), int(fixed_iters), int(norm))
+        ctl = _Control(float(tol), int(max_iters), int(fixed_iters), int(norm), int(ordering))
         info = _Info()
         phi = np.empty((self.J, self.G, 4))
         cap = fixed_iters if fixed_iters > 0 else max_iters
@@ -226,7 +230,7 @@ class Oracle:
         return phi, out
 
     def run(self, method, steps=None, tol=1e-10, max_iters=100000, fixed_iters=None,
-            norm=NORM_SCALAR, q=None, inc_l=None, inc_r=None, psi_init=None):
+            norm=NORM_SCALAR, q=None, inc_l=None, inc_r=None, psi_init=None, ordering=ORDER_JACOBI):
         """Run `steps` time steps; fixed_iters may be a per-step list (lock-step)."""
         p = self.p
         steps = p["steps"] if steps is None else steps
@@ -240,7 +244,8 @@ class Oracle:
             if fixed_iters is not None:
                 fi = fixed_iters[k] if np.ndim(fixed_iters) else int(fixed_iters)
             phi, info = self.step(method, psi_prev, psi_iter, q=q, inc_l=inc_l, inc_r=inc_r,
-                                  tol=tol, max_iters=max_iters, fixed_iters=fi, norm=norm)
+                                  tol=tol, max_iters=max_iters, fixed_iters=fi, norm=norm,
+                                  ordering=ordering)
             phis.append(phi)
             infos.append(info)
         return dict(phi=np.stack(phis), info=infos, psi_prev=psi_prev, psi_iter=psi_iter)

@@ -21,6 +21,7 @@ enum {
 };
 
 enum { ORC_NORM_SCALAR = 0, ORC_NORM_ANGULAR = 1 };
+enum { ORC_ORDER_JACOBI = 0, ORC_ORDER_RED_BLACK = 1 };
 
 typedef struct {
     int J, N, G;
@@ -34,6 +35,7 @@ typedef struct {
     int max_iters;         /* cap; reaching it reports ORC_NOT_CONVERGED */
     int fixed_iters;       /* > 0: run exactly this many iterations, no test */
     int norm;              /* ORC_NORM_SCALAR (default) or ORC_NORM_ANGULAR */
+    int ordering;          /* ORC_ORDER_JACOBI (default) or ORC_ORDER_RED_BLACK */
 } orc_control;
 
 typedef struct {
@@ -51,6 +53,10 @@ int orc_oci_iterate(const orc_problem *p, const double *lu, const int *piv,
                     const double *q, const double *q_ang, const double *psi_prev,
                     const double *inc_l, const double *inc_r,
                     const double *psi_in, double *psi_out);
+int orc_oci_iterate_rb(const orc_problem *p, const double *lu, const int *piv,
+                       const double *q, const double *q_ang, const double *psi_prev,
+                       const double *inc_l, const double *inc_r,
+                       const double *psi_in, double *psi_out);
 int orc_oci_step(const orc_problem *p, const orc_control *c,
                  const double *lu, const int *piv,
                  const double *q, const double *q_ang,

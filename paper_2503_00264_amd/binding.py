@@ -22,11 +22,14 @@ OCI_ERR_INVALID, OCI_ERR_HIP, OCI_ERR_SINGULAR = -1, -2, -3
 OCI_ERR_WORKSPACE, OCI_ERR_UNSUPPORTED, OCI_ERR_DEVICE = -4, -5, -6
 OCI_FP64, OCI_FP32_REFINED = 0, 1
 OCI_NORM_SCALAR, OCI_NORM_ANGULAR = 0, 1
+OCI_SOLVE_DENSE, OCI_SOLVE_STRUCTURED = 0, 1
+OCI_ORDER_JACOBI, OCI_ORDER_RED_BLACK = 0, 1
+OCI_BOUNDARY_INCIDENT, OCI_BOUNDARY_PERIODIC = 0, 1
 
 # every symbol include/oci.h declares
 EXPORTS = ("oci_workspace_bytes", "oci_setup", "oci_set_state", "oci_get_state",
-           "oci_step", "oci_run_steps", "si_step", "oci_profile_enable", "oci_profile_read",
-           "oci_autotune", "oci_get_config", "oci_destroy", "oci_batch_workspace_bytes", "oci_batch_setup", "oci_batch_bind",
+           "oci_step", "oci_run_steps", "oci_capture_steps", "oci_replay_steps", "si_step", "oci_profile_enable", "oci_profile_read",
+           "oci_autotune", "oci_set_history", "oci_get_config", "oci_destroy", "oci_batch_workspace_bytes", "oci_batch_setup", "oci_batch_bind", "oci_batch_bind_steps",
            "oci_batch_step", "oci_batch_capture", "oci_batch_replay", "oci_batch_set_state",
            "oci_batch_get_state", "oci_batch_rebalance", "oci_batch_info", "oci_batch_destroy", "oci_status_string")
 
@@ -43,7 +46,8 @@ class oci_desc(C.Structure):
                 ("sigma_s", C.c_void_p), ("speed", C.c_void_p),
                 ("dt", C.c_double), ("tol", C.c_double),
                 ("max_iters", C.c_int32), ("fixed_iters", C.c_int32),
-                ("precision", C.c_int32), ("norm", C.c_int32)]
+                ("precision", C.c_int32), ("norm", C.c_int32), ("solver", C.c_int32),
+                ("ordering", C.c_int32), ("boundary", C.c_int32)]
 
 
 class oci_step_info(C.Structure):
@@ -69,16 +73,21 @@ def lib():
         L.oci_set_state.argtypes = [vp, vp]
         L.oci_get_state.argtypes = [vp, vp]
         L.oci_step.argtypes = [vp] * 7
-        L.oci_run_steps.argtypes = [vp, i32] + [vp] * 6
+        i64 = C.c_int64
+        L.oci_run_steps.argtypes = [vp, i32, vp, i64, vp, vp, i64, vp, vp, vp]
+        L.oci_capture_steps.argtypes = [vp, i32] + [vp] * 6
+        L.oci_replay_steps.argtypes = [vp]
         L.si_step.argtypes = [vp] * 7
         L.oci_profile_enable.argtypes = [vp, i32]
         L.oci_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.oci_destroy.argtypes = [vp]
         L.oci_autotune.argtypes = [vp, i32, vp]
         L.oci_get_config.argtypes = [vp, vp]
+        L.oci_set_history.argtypes = [vp, vp, i32]
         L.oci_batch_workspace_bytes.argtypes = [i32, vp, C.POINTER(C.c_size_t)]
         L.oci_batch_setup.argtypes = [i32, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.oci_batch_bind.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.oci_batch_bind_steps.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.oci_batch_step.argtypes = [vp]
         L.oci_batch_capture.argtypes = [vp, i32]
         L.oci_batch_replay.argtypes = [vp]
@@ -120,7 +129,8 @@ def oci_status_string(code):
 
 
 def make_desc(prob, tol=1e-10, max_iters=100000, fixed_iters=0,
-              precision=OCI_FP64, norm=OCI_NORM_SCALAR, dt=None):
+              precision=OCI_FP64, norm=OCI_NORM_SCALAR, dt=None, solver=OCI_SOLVE_DENSE,
+              ordering=OCI_ORDER_JACOBI, boundary=OCI_BOUNDARY_INCIDENT):
     """Build an oci_desc from a workload dict; the returned keep-alive tuple
     holds the host arrays the descriptor points to."""
     arrs = tuple(np.ascontiguousarray(prob[k], dtype=np.float64)
@@ -128,7 +138,7 @@ def make_desc(prob, tol=1e-10, max_iters=100000, fixed_iters=0,
     d = oci_desc(int(prob["J"]), int(prob["N"]), int(prob["G"]),
                  *[a.ctypes.data for a in arrs],
                  float(prob["dt"] if dt is None else dt), float(tol), int(max_iters),
-                 int(fixed_iters), int(precision), int(norm))
+                 int(fixed_iters), int(precision), int(norm), int(solver), int(ordering), int(boundary))
     return d, arrs
 
 
@@ -158,9 +168,24 @@ def oci_step(h, q, inc_left, inc_right, phi_out, psi_out, info):
                                              _ptr(phi_out), _ptr(psi_out), _ptr(info)))
 
 
-def oci_run_steps(h, nsteps, q, inc_left, inc_right, phi_out, psi_out, info):
-    return _check("oci_run_steps", lib().oci_run_steps(h, nsteps, _ptr(q), _ptr(inc_left), _ptr(inc_right),
-                                                       _ptr(phi_out), _ptr(psi_out), _ptr(info)))
+def oci_run_steps(h, nsteps, q, inc_left, inc_right, phi_out, psi_out, info, q_stride=0, inc_stride=0):
+    """nsteps steps; with strides (in elements) q and the incident fluxes
+    hold one array per step, else the same ones serve every step."""
+    return _check("oci_run_steps", lib().oci_run_steps(h, nsteps, _ptr(q), int(q_stride), _ptr(inc_left),
+                                                       _ptr(inc_right), int(inc_stride), _ptr(phi_out),
+                                                       _ptr(psi_out), _ptr(info)))
+
+
+def oci_capture_steps(h, n_steps, q, inc_left, inc_right, phi_out, psi_out, info):
+    """q, inc_left, inc_right, psi_out: lists of n_steps tensors (entries may
+    be None) or None; phi_out: list of n_steps tensors; info: n_steps records."""
+    _check("oci_capture_steps", lib().oci_capture_steps(h, int(n_steps), _ptr_array(q), _ptr_array(inc_left),
+                                                        _ptr_array(inc_right), _ptr_array(phi_out),
+                                                        _ptr_array(psi_out), _ptr(info)))
+
+
+def oci_replay_steps(h):
+    _check("oci_replay_steps", lib().oci_replay_steps(h))
 
 
 def si_step(h, q, inc_left, inc_right, phi_out, psi_out, info):
@@ -186,6 +211,13 @@ def oci_autotune(h, iters=8):
     cfg = (C.c_int32 * 6)()
     _check("oci_autotune", lib().oci_autotune(h, int(iters), cfg))
     return dict(zip(CONFIG_FIELDS, list(cfg)))
+
+
+def oci_set_history(h, e_hist, capacity=None):
+    """Record e_l of every iteration of later steps into e_hist (a float64
+    device tensor), or stop recording (e_hist None)."""
+    cap = 0 if e_hist is None else int(e_hist.numel() if capacity is None else capacity)
+    _check("oci_set_history", lib().oci_set_history(h, _ptr(e_hist), cap))
 
 
 def oci_get_config(h):
@@ -227,6 +259,14 @@ def _ptr_array(xs):
 def oci_batch_bind(b, q, inc_left, inc_right, phi_out, info):
     _check("oci_batch_bind", lib().oci_batch_bind(b, _ptr_array(q), _ptr_array(inc_left),
                                                   _ptr_array(inc_right), _ptr_array(phi_out), _ptr(info)))
+
+
+def oci_batch_bind_steps(b, n_steps, q, inc_left, inc_right, phi_out, info):
+    """Per-step argument sets: q, inc_left, inc_right, phi_out are lists of
+    n_steps * nslab tensors (or None), entry i * nslab + k for step i, slab k."""
+    _check("oci_batch_bind_steps", lib().oci_batch_bind_steps(b, int(n_steps), _ptr_array(q), _ptr_array(inc_left),
+                                                              _ptr_array(inc_right), _ptr_array(phi_out),
+                                                              _ptr(info)))
 
 
 def oci_batch_step(b):
@@ -280,7 +320,8 @@ class Solver:
     """
 
     def __init__(self, prob, precision=OCI_FP64, tol=1e-10, max_iters=100000,
-                 fixed_iters=0, norm=OCI_NORM_SCALAR, stream=None, dt=None):
+                 fixed_iters=0, norm=OCI_NORM_SCALAR, stream=None, dt=None, solver=OCI_SOLVE_DENSE,
+                 ordering=OCI_ORDER_JACOBI, boundary=OCI_BOUNDARY_INCIDENT):
         import torch
         self.torch = torch
         self.prob = prob
@@ -289,7 +330,8 @@ class Solver:
         self.stream = torch.cuda.current_stream() if stream is None else stream
         self.desc, self._keep = make_desc(prob, tol=tol, max_iters=max_iters,
                                           fixed_iters=fixed_iters, precision=precision,
-                                          norm=norm, dt=dt)
+                                          norm=norm, dt=dt, solver=solver, ordering=ordering,
+                                          boundary=boundary)
         self.ws_bytes = oci_workspace_bytes(self.desc)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
         off = (-self.ws.data_ptr()) % 256
@@ -354,8 +396,12 @@ class Solver:
         return phis.cpu().numpy(), [decode_info(raw[k]) for k in range(steps)]
 
     def autotune(self, iters=8):
-        """Pick the fastest launch shape (state is zero afterwards)."""
-        return oci_autotune(self.h, iters)
+        """Pick the fastest launch shape.  oci_autotune leaves the state at
+        zero, so the problem's initial state (if any) is applied again."""
+        cfg = oci_autotune(self.h, iters)
+        if self.prob.get("psi_init") is not None and np.any(self.prob["psi_init"]):
+            self.set_state(self.prob["psi_init"])
+        return cfg
 
     def config(self):
         return oci_get_config(self.h)
@@ -381,14 +427,14 @@ class BatchSolver:
     """
 
     def __init__(self, probs, precision=OCI_FP32_REFINED, tol=1e-10, max_iters=100000,
-                 fixed_iters=0, stream=None):
+                 fixed_iters=0, stream=None, solver=OCI_SOLVE_DENSE, ordering=OCI_ORDER_JACOBI):
         import torch
         self.torch = torch
         self.probs = probs
         self.dev = torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.Stream() if stream is None else stream
         made = [make_desc(p, tol=tol, max_iters=max_iters, fixed_iters=fixed_iters,
-                          precision=precision) for p in probs]
+                          precision=precision, solver=solver, ordering=ordering) for p in probs]
         self.descs = [d for d, _ in made]
         self._keep = [k for _, k in made]
         self.ws_bytes = oci_batch_workspace_bytes(self.descs)
@@ -406,11 +452,47 @@ class BatchSolver:
             self.info = torch.zeros(24 * len(probs), dtype=torch.uint8, device=self.dev)
         self.stream.synchronize()
         oci_batch_bind(self.b, self.q, self.inc_l, self.inc_r, self.phi, self.info)
+        for k, p in enumerate(probs):
+            if p.get("psi_init") is not None and np.any(p["psi_init"]):
+                self.set_state(k, p["psi_init"])
 
     def _dev(self, a):
         if a is None:
             return None
         return self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(self.dev)
+
+    def bind_steps(self, n_steps, q=None, inc_left=None, inc_right=None):
+        """Bind n_steps argument sets: per-step outputs (self.phi_steps[i][k],
+        self.info_steps) and, optionally, per-step sources given as lists of
+        n_steps lists of per-slab arrays (None: the problem's own, every step)."""
+        t = self.torch
+        ns = len(self.probs)
+        f64 = dict(dtype=t.float64, device=self.dev)
+
+        def per_step(arg, own):
+            if arg is None:
+                return [own[k] for _ in range(n_steps) for k in range(ns)]
+            return [self._dev(arg[i][k]) for i in range(n_steps) for k in range(ns)]
+
+        with t.cuda.stream(self.stream):
+            self._step_q = per_step(q, self.q)
+            self._step_l = per_step(inc_left, self.inc_l)
+            self._step_r = per_step(inc_right, self.inc_r)
+            self.phi_steps = [[t.zeros((p["J"], p["G"], 4), **f64) for p in self.probs] for _ in range(n_steps)]
+            self.info_steps = t.zeros(24 * ns * n_steps, dtype=t.uint8, device=self.dev)
+        self.stream.synchronize()
+        oci_batch_bind_steps(self.b, n_steps, self._step_q, self._step_l, self._step_r,
+                             [f for row in self.phi_steps for f in row], self.info_steps)
+        self.n_bound = n_steps
+
+    def step_results(self):
+        """(phi [step][slab] as numpy, info [step][slab]) of the bound argument sets."""
+        self.stream.synchronize()
+        raw = self.info_steps.cpu().numpy()
+        ns = len(self.probs)
+        return ([[f.cpu().numpy() for f in row] for row in self.phi_steps],
+                [[decode_info(raw[24 * (i * ns + k):24 * (i * ns + k + 1)]) for k in range(ns)]
+                 for i in range(self.n_bound)])
 
     def step(self):
         oci_batch_step(self.b)

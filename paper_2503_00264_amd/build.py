@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liboci.so")
-SOURCES = ["oci_api.hip", "oci_setup.hip", "oci_step.hip"]
+SOURCES = ["oci_api.hip", "oci_setup.hip", "oci_step.hip", "oci_wb.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -15,7 +15,7 @@
 
 namespace oci {
 hipError_t launch_setup(const Slab &S, bool fp32, hipStream_t st);
-hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, hipStream_t st, int local_nwg);
+hipError_t launch_begin(const Slab &S, const StepIO &io, int broadcast, hipStream_t st, int local_nwg);
 hipError_t launch_open(const Slab &S, const StepIO &io, hipStream_t st, int local_nwg);
 hipError_t launch_end(const Slab &S, const StepIO &io, hipStream_t st);
 hipError_t launch_oci_step(const Slab &S, const StepIO &io, bool fp32, int np, bool res, int bs, int nwg, int ntiles,
@@ -31,9 +31,15 @@ hipError_t launch_si_iteration(const Slab &S, const StepIO &io, hipStream_t st);
 size_t si_flux_blocks(const Slab &S);
 hipError_t batch_occupancy(bool fp32, int *blocks);
 int batch_block();
-hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp32, bool broadcast, hipStream_t st,
-                             bool coop);
+hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp32, bool structured, bool broadcast,
+                             hipStream_t st, bool coop);
+hipError_t wb_batch_occupancy(int *blocks);
 hipError_t launch_flag_broadcast(const Slab &S, hipStream_t st);
+hipError_t launch_wb_setup(const Slab &S, hipStream_t st);
+hipError_t launch_oci_wb(const Slab &S, const StepIO &io, int nwg, int ntiles, hipStream_t st);
+hipError_t wb_occupancy(int NG, int *blocks);
+int wb_cells_per_tile(int NG);
+int wb_block();
 }  // namespace oci
 
 using namespace oci;
@@ -52,10 +58,12 @@ struct oci_handle {
     int max_wg;            // cap on its workgroups (0: none; testing override)
     bool resident;
     bool local;            // workgroup-local kernel (iterate kept in LDS)
+    bool structured;       // structured cell solve (OCI_SOLVE_STRUCTURED)
     size_t dyn_lds;        // its dynamic LDS bytes
     bool need_broadcast;   // next step starts from psi_prev on both levels
-    int32_t *h_flag;       // pinned host word for SI's convergence polling
+    int32_t h_flag;        // host copy of the done flag for SI's convergence polling
     bool profiling;
+    hipGraphExec_t graph;              // steps captured by oci_capture_steps
     std::vector<hipEvent_t> ev_pool;   // recorded pairs: [2k] start, [2k+1] stop
     size_t ev_used;
     int32_t prof_steps;                // time steps those pairs cover
@@ -96,6 +104,14 @@ static int check_desc(const oci_desc *d) {
     if (d->max_iters < 1 || d->fixed_iters < 0) return OCI_ERR_INVALID;
     if (d->precision != OCI_FP64 && d->precision != OCI_FP32_REFINED) return OCI_ERR_INVALID;
     if (d->norm != OCI_NORM_SCALAR && d->norm != OCI_NORM_ANGULAR) return OCI_ERR_INVALID;
+    if (d->solver != OCI_SOLVE_DENSE && d->solver != OCI_SOLVE_STRUCTURED) return OCI_ERR_INVALID;
+    if (d->ordering != OCI_ORDER_JACOBI && d->ordering != OCI_ORDER_RED_BLACK) return OCI_ERR_INVALID;
+    if (d->boundary != OCI_BOUNDARY_INCIDENT && d->boundary != OCI_BOUNDARY_PERIODIC) return OCI_ERR_INVALID;
+    if (d->solver == OCI_SOLVE_STRUCTURED &&
+        (d->precision != OCI_FP64 || d->norm != OCI_NORM_SCALAR || d->G > 8))
+        return OCI_ERR_UNSUPPORTED;
+    if (d->solver != OCI_SOLVE_STRUCTURED && (d->ordering != OCI_ORDER_JACOBI || d->boundary != OCI_BOUNDARY_INCIDENT))
+        return OCI_ERR_UNSUPPORTED;
     const size_t J = d->J, G = d->G;
     if (!finite_nonneg(d->dx, J, true)) return OCI_ERR_INVALID;
     if (!finite_nonneg(d->sigma_t, J * G, false)) return OCI_ERR_INVALID;
@@ -145,7 +161,7 @@ static void gauss_legendre(int N, double *mu, double *w) {
 // --------------------------------------------------------------- workspace
 struct Layout {
     size_t ctl, bar, mu, w, dx, st, ss, sp, X, psi0, psi1, phi0, phi1, prev, crhs, exch, linv, resp, msw, alpha, ein,
-        part, total;
+        part, wb, edge, total;
     int bar_groups;
 };
 
@@ -172,7 +188,8 @@ static Layout layout(const oci_desc *d, int num_cu) {
     L.st = take(J * G * 8);
     L.ss = take(J * G * G * 8);
     L.sp = take(G * 8);
-    L.X = take(J * np * np * es);
+    const bool structured = d->solver == OCI_SOLVE_STRUCTURED;
+    L.X = take(structured ? 0 : J * np * np * es);
     L.psi0 = take(J * n * 8);
     L.psi1 = take(J * n * 8);
     L.phi0 = take(J * G * 4 * 8);
@@ -189,6 +206,8 @@ static Layout layout(const oci_desc *d, int num_cu) {
     size_t parts = (size_t)num_cu * 8 * kPartSlots;   // the local kernel's ring of partial sums
     if (si_blocks > parts) parts = si_blocks;
     L.part = take(parts * 8);
+    L.wb = take(structured ? J * 16 * G * G * 8 : 0);   // [J][4G][2G] complex
+    L.edge = take(structured ? 2 * J * N * G * 2 * 8 : 0);
     L.total = o;
     return L;
 }
@@ -210,7 +229,30 @@ extern "C" int oci_workspace_bytes(const oci_desc *desc, size_t *bytes) {
 // the workgroup-local kernel (iterate in LDS) with register-resident
 // inverse rows, then local with streamed rows, then the global-memory kernel
 // (resident, then streamed).  One tile = block / (threads per cell) cells.
+static int configure_structured(oci_handle *h, int gsz) {
+    const int NG = h->d.N * h->d.G;
+    const int cpt = wb_cells_per_tile(NG);
+    const long cells = h->S.ordering == OCI_ORDER_RED_BLACK ? (h->d.J + 1) / 2 : h->d.J;   // per half-sweep
+    const long ntiles = (cells + cpt - 1) / cpt;
+    long cap = (long)h->num_cu * 8;   // partial-sum and barrier slots in the workspace
+    if (h->max_wg > 0 && h->max_wg < cap) cap = h->max_wg;
+    int occ = 0;
+    if (wb_occupancy(NG, &occ) != hipSuccess || occ < 1) return OCI_ERR_HIP;
+    if ((long)occ * h->num_cu < cap) cap = (long)occ * h->num_cu;
+    const long nwg = ntiles < cap ? ntiles : cap;
+    h->block = wb_block();
+    h->ntiles = (int)ntiles;
+    h->nwg = (int)nwg;
+    h->local = false;
+    h->resident = false;
+    h->dyn_lds = 0;
+    h->S.bar_gsz = gsz;
+    h->S.bar_groups = (h->nwg + gsz - 1) / gsz;
+    return OCI_OK;
+}
+
 static int configure(oci_handle *h, int block, bool allow_local, bool allow_res, int gsz) {
+    if (h->structured) return configure_structured(h, gsz);
     const int num_cu = h->num_cu;
     const int N = h->d.N, G = h->d.G;
     const int rpt = h->np > block ? h->np / block : 1;
@@ -305,10 +347,6 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
     h->ws = (unsigned char *)workspace_dev;
     h->ws_bytes = workspace_bytes;
     if (hipGetDevice(&h->device) != hipSuccess) { delete h; return OCI_ERR_HIP; }
-    if (hipHostMalloc((void **)&h->h_flag, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
-        delete h;
-        return OCI_ERR_HIP;
-    }
 
     unsigned char *ws = h->ws;
     Slab &S = h->S;
@@ -334,6 +372,9 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
     S.si_alpha = (double *)(ws + L.alpha);
     S.si_ein = (double *)(ws + L.ein);
     S.partials = (double *)(ws + L.part);
+    S.wb = desc->solver == OCI_SOLVE_STRUCTURED ? (double *)(ws + L.wb) : nullptr;
+    S.edge = desc->solver == OCI_SOLVE_STRUCTURED ? (double *)(ws + L.edge) : nullptr;
+    h->structured = S.wb != nullptr;
     S.ctl = (Ctl *)(ws + L.ctl);
     S.bar = (uint64_t *)(ws + L.bar);
     S.bar_groups = L.bar_groups;
@@ -341,6 +382,15 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
     if (const char *env = getenv("OCI_BAR_GROUP")) {
         const int g = atoi(env);
         if (g >= 1 && g <= 4096) S.bar_gsz = g;
+    }
+    S.zero_cell = -1;
+    S.ordering = desc->ordering;
+    S.periodic = desc->boundary == OCI_BOUNDARY_PERIODIC ? 1 : 0;
+    S.hist = nullptr;
+    S.hist_cap = 0;
+    if (const char *env = getenv("OCI_TEST_ZERO_PIVOT_CELL")) {   // test hook (singular-cell path)
+        const int j = atoi(env);
+        if (j >= 0 && j < desc->J) S.zero_cell = j;
     }
     S.tol = desc->tol;
     S.max_iters = desc->max_iters;
@@ -366,6 +416,7 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
     if (e == hipSuccess) e = hipMemsetAsync(ws + L.ctl, 0, L.mu - L.ctl, st);
     if (e == hipSuccess) e = hipMemsetAsync(ws + L.psi0, 0, L.prev + J * h->n / 2 * 8 - L.psi0, st);
     if (e == hipSuccess) e = launch_setup(S, h->fp32, st);
+    if (e == hipSuccess && h->structured) e = launch_wb_setup(S, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     free(mu);
     if (e != hipSuccess) { oci_destroy(h); return OCI_ERR_HIP; }
@@ -427,7 +478,9 @@ extern "C" int oci_step(oci_handle *h, const double *q_dev, const double *inc_le
     h->need_broadcast = false;
     hipEvent_t e0 = h->profiling ? prof_event(h) : nullptr, e1 = h->profiling ? prof_event(h) : nullptr;
     if (e0) HIPCHECK(hipEventRecord(e0, h->st));
-    if (h->local)
+    if (h->structured)
+        HIPCHECK(launch_oci_wb(h->S, io, h->nwg, h->ntiles, h->st));
+    else if (h->local)
         HIPCHECK(launch_oci_local(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->dyn_lds, h->st));
     else
         HIPCHECK(launch_oci_step(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->st, true));
@@ -437,16 +490,18 @@ extern "C" int oci_step(oci_handle *h, const double *q_dev, const double *inc_le
     return OCI_OK;
 }
 
-extern "C" int oci_run_steps(oci_handle *h, int32_t nsteps, const double *q_dev, const double *inc_left_dev,
-                             const double *inc_right_dev, double *phi_out_dev, double *psi_out_dev,
-                             oci_step_info *info_dev) {
-    if (nsteps < 1) return OCI_ERR_INVALID;
+extern "C" int oci_run_steps(oci_handle *h, int32_t nsteps, const double *q_dev, int64_t q_stride,
+                             const double *inc_left_dev, const double *inc_right_dev, int64_t inc_stride,
+                             double *phi_out_dev, double *psi_out_dev, oci_step_info *info_dev) {
+    if (nsteps < 1 || q_stride < 0 || inc_stride < 0) return OCI_ERR_INVALID;
     int rc = check_step_args(h, phi_out_dev, info_dev);
     if (rc) return rc;
     const size_t phi_stride = (size_t)h->d.J * h->d.G * 4;
+    auto step_src = [](const double *p, int64_t stride, int k) { return p ? p + (size_t)k * stride : p; };
     if (!(h->local && h->resident) || nsteps == 1) {
         for (int k = 0; k < nsteps; ++k) {
-            rc = oci_step(h, q_dev, inc_left_dev, inc_right_dev, phi_out_dev + k * phi_stride,
+            rc = oci_step(h, step_src(q_dev, q_stride, k), step_src(inc_left_dev, inc_stride, k),
+                          step_src(inc_right_dev, inc_stride, k), phi_out_dev + k * phi_stride,
                           k == nsteps - 1 ? psi_out_dev : nullptr, info_dev + k);
             if (rc) return rc;
         }
@@ -454,9 +509,9 @@ extern "C" int oci_run_steps(oci_handle *h, int32_t nsteps, const double *q_dev,
     }
     // one launch of the register-resident kernel for all steps; the first
     // step opens and the last closes as in oci_step, the others turn over
-    // inside the kernel
-    StepIO io{q_dev, inc_left_dev, inc_right_dev, phi_out_dev, nullptr, info_dev, nsteps};
-    if (h->need_broadcast) HIPCHECK(launch_begin(h->S, io, true, h->st, h->nwg));
+    // inside the kernel (each taking its own sources through the strides)
+    StepIO io{q_dev, inc_left_dev, inc_right_dev, phi_out_dev, nullptr, info_dev, nsteps, 0, q_stride, inc_stride};
+    if (h->need_broadcast) HIPCHECK(launch_begin(h->S, io, 1, h->st, h->nwg));
     else HIPCHECK(launch_open(h->S, io, h->st, h->nwg));
     h->need_broadcast = false;
     hipEvent_t e0 = h->profiling ? prof_event(h) : nullptr, e1 = h->profiling ? prof_event(h) : nullptr;
@@ -464,9 +519,62 @@ extern "C" int oci_run_steps(oci_handle *h, int32_t nsteps, const double *q_dev,
     HIPCHECK(launch_oci_local(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->dyn_lds, h->st));
     if (e1) HIPCHECK(hipEventRecord(e1, h->st));
     if (e1) h->prof_steps += nsteps;
-    const StepIO last{q_dev, inc_left_dev, inc_right_dev, phi_out_dev + (nsteps - 1) * phi_stride, psi_out_dev,
-                      info_dev + (nsteps - 1), 1};
+    const int kl = nsteps - 1;
+    const StepIO last{step_src(q_dev, q_stride, kl), step_src(inc_left_dev, inc_stride, kl),
+                      step_src(inc_right_dev, inc_stride, kl), phi_out_dev + kl * phi_stride, psi_out_dev,
+                      info_dev + kl, 1};
     HIPCHECK(launch_end(h->S, last, h->st));
+    return OCI_OK;
+}
+
+// The iteration kernels of one step as oci_step launches them, with the
+// opening deciding on the device whether to start from the state (steps in
+// a graph cannot ask the host), and no cooperative launch (not capturable).
+static hipError_t enqueue_step_for_graph(oci_handle *h, const StepIO &io) {
+    hipError_t e = launch_begin(h->S, io, 2, h->st, h->local ? h->nwg : 0);
+    if (e != hipSuccess) return e;
+    if (h->structured) e = launch_oci_wb(h->S, io, h->nwg, h->ntiles, h->st);
+    else if (h->local)
+        e = launch_oci_local(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->dyn_lds, h->st);
+    else e = launch_oci_step(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->st, false);
+    if (e != hipSuccess) return e;
+    return launch_end(h->S, io, h->st);
+}
+
+extern "C" int oci_capture_steps(oci_handle *h, int32_t n_steps, const double *const *q_dev,
+                                 const double *const *inc_left_dev, const double *const *inc_right_dev,
+                                 double *const *phi_out_dev, double *const *psi_out_dev, oci_step_info *info_dev) {
+    if (!h || n_steps < 1 || !phi_out_dev || !info_dev || !h->st) return OCI_ERR_INVALID;
+    for (int k = 0; k < n_steps; ++k)
+        if (!phi_out_dev[k]) return OCI_ERR_INVALID;
+    if (h->graph) { (void)hipGraphExecDestroy(h->graph); h->graph = nullptr; }
+    HIPCHECK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+        const StepIO io{q_dev ? q_dev[k] : nullptr, inc_left_dev ? inc_left_dev[k] : nullptr,
+                        inc_right_dev ? inc_right_dev[k] : nullptr, phi_out_dev[k],
+                        psi_out_dev ? psi_out_dev[k] : nullptr, info_dev + k, 1};
+        e = enqueue_step_for_graph(h, io);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(h->st, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return OCI_ERR_HIP;
+    }
+    e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { h->graph = nullptr; return OCI_ERR_HIP; }
+    return OCI_OK;
+}
+
+extern "C" int oci_replay_steps(oci_handle *h) {
+    if (!h || !h->graph) return OCI_ERR_INVALID;
+    if (h->need_broadcast) {   // the state was replaced: the graph's first step starts from it
+        HIPCHECK(launch_flag_broadcast(h->S, h->st));
+        h->need_broadcast = false;
+    }
+    HIPCHECK(hipGraphLaunch(h->graph, h->st));
     return OCI_OK;
 }
 
@@ -488,9 +596,9 @@ extern "C" int si_step(oci_handle *h, const double *q_dev, const double *inc_lef
         for (int i = 0; i < k; ++i) HIPCHECK(launch_si_iteration(h->S, io, h->st));
         launched += k;
         if (launched >= cap) break;
-        HIPCHECK(hipMemcpyAsync(h->h_flag, &h->S.ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+        HIPCHECK(hipMemcpyAsync(&h->h_flag, &h->S.ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
         HIPCHECK(hipStreamSynchronize(h->st));
-        if (*h->h_flag) break;
+        if (h->h_flag) break;
         if (batch < 64) batch *= 2;
     }
     if (e1) HIPCHECK(hipEventRecord(e1, h->st));
@@ -529,6 +637,11 @@ extern "C" int oci_profile_read(oci_handle *h, double *ms, int32_t *steps) {
 // afterwards.
 extern "C" int oci_autotune(oci_handle *h, int32_t iters, int32_t *config) {
     if (!h || iters < 1) return OCI_ERR_INVALID;
+    if (h->structured) {   // one launch shape: nothing to choose
+        if (oci_set_state(h, nullptr) != OCI_OK) return OCI_ERR_HIP;
+        if (config) oci_get_config(h, config);
+        return OCI_OK;
+    }
     struct Cand { int block; bool local, res; int gsz; };
     std::vector<Cand> cands;
     for (int block : {1024, 256})
@@ -579,6 +692,13 @@ extern "C" int oci_autotune(oci_handle *h, int32_t iters, int32_t *config) {
     return OCI_OK;
 }
 
+extern "C" int oci_set_history(oci_handle *h, double *e_hist_dev, int32_t capacity) {
+    if (!h || (e_hist_dev && capacity < 1)) return OCI_ERR_INVALID;
+    h->S.hist = e_hist_dev;
+    h->S.hist_cap = e_hist_dev ? capacity : 0;
+    return OCI_OK;
+}
+
 extern "C" int oci_get_config(const oci_handle *h, int32_t *config) {
     if (!h || !config) return OCI_ERR_INVALID;
     config[0] = h->block;
@@ -593,37 +713,47 @@ extern "C" int oci_get_config(const oci_handle *h, int32_t *config) {
 extern "C" int oci_destroy(oci_handle *h) {
     if (!h) return OCI_ERR_INVALID;
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
-    if (h->h_flag) (void)hipHostFree(h->h_flag);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
     delete h;
     return OCI_OK;
 }
 
 // ================================================================ batches
+// Step argument sets a batch can hold at once (one launch table each).
+constexpr int kMaxBatchSteps = 64;
+
 struct oci_batch {
     int nslab;
     bool fp32;
+    bool structured;
     hipStream_t st;
     std::vector<oci_handle *> slabs;
-    std::vector<BatchEntry> tab;   // host copy of the device table
-    BatchEntry *d_tab;             // in the workspace
+    std::vector<BatchEntry> tab;   // host copy of the device tables, [nbound][nslab]
+    BatchEntry *d_tab;             // in the workspace: kMaxBatchSteps tables, tstride bytes apart
+    size_t tstride;
+    int nbound;                    // bound step argument sets (0: none)
+    int cursor;                    // argument set of the next eager step
+    int last;                      // argument set of the last step enqueued (-1: none)
     int nwg;                       // workgroups of the batched launch
     int occ;                       // co-resident batch workgroups per CU
-    bool bound;
-    oci_step_info *info_dev;       // bound per-slab results
+    oci_step_info *info_dev;       // bound results, [nbound][nslab]
     hipGraphExec_t graph;
-    int graph_steps;
+    int graph_steps, graph_first;  // captured steps and the argument set of the first
 };
 
 static size_t batch_table_bytes(int nslab) { return align256((size_t)nslab * sizeof(BatchEntry)); }
+static const BatchEntry *batch_dtab(const oci_batch *b, int i) {
+    return (const BatchEntry *)((const unsigned char *)b->d_tab + (size_t)i * b->tstride);
+}
 
 extern "C" int oci_batch_workspace_bytes(int32_t nslab, const oci_desc *descs, size_t *bytes) {
     if (nslab < 1 || !descs || !bytes) return OCI_ERR_INVALID;
-    size_t tot = batch_table_bytes(nslab);
+    size_t tot = (size_t)kMaxBatchSteps * batch_table_bytes(nslab);
     for (int k = 0; k < nslab; ++k) {
         size_t b = 0;
         const int rc = oci_workspace_bytes(&descs[k], &b);
         if (rc) return rc;
-        if (descs[k].precision != descs[0].precision) return OCI_ERR_INVALID;
+        if (descs[k].precision != descs[0].precision || descs[k].solver != descs[0].solver) return OCI_ERR_INVALID;
         tot += align256(b);
     }
     *bytes = tot;
@@ -653,8 +783,9 @@ static int batch_allocate(oci_batch *b, const std::vector<double> &weight) {
     for (int k = 0; k < nslab; ++k) {
         const oci_handle *h = b->slabs[k];
         const int rpt = h->np > bs ? h->np / bs : 1;
-        const int cpt = bs / (h->np / rpt);
-        ntile[k] = (h->d.J + cpt - 1) / cpt;
+        const int cpt = b->structured ? wb_cells_per_tile(h->d.N * h->d.G) : bs / (h->np / rpt);
+        const long cells = h->S.ordering == OCI_ORDER_RED_BLACK ? (h->d.J + 1) / 2 : h->d.J;
+        ntile[k] = (cells + cpt - 1) / cpt;
         wsum += weight[k];
     }
     long used = 0;
@@ -672,16 +803,29 @@ static int batch_allocate(oci_batch *b, const std::vector<double> &weight) {
         --used;
     }
     int wg0 = 0;
+    const int nsets = b->nbound > 0 ? b->nbound : 1;
     for (int k = 0; k < nslab; ++k) {
-        BatchEntry &e = b->tab[k];
-        e.S.bar_groups = (int)((alloc[k] + e.S.bar_gsz - 1) / e.S.bar_gsz);
-        e.ntiles = (int)ntile[k];
-        e.wg0 = wg0;
-        e.nwg = (int)alloc[k];
-        wg0 += e.nwg;
+        for (int i = 0; i < nsets; ++i) {
+            BatchEntry &e = b->tab[(size_t)i * nslab + k];
+            e.S.bar_groups = (int)((alloc[k] + e.S.bar_gsz - 1) / e.S.bar_gsz);
+            e.ntiles = (int)ntile[k];
+            e.wg0 = wg0;
+            e.nwg = (int)alloc[k];
+        }
+        wg0 += (int)alloc[k];
     }
     b->nwg = wg0;
     return OCI_OK;
+}
+
+static hipError_t batch_upload(oci_batch *b) {
+    const int nsets = b->nbound > 0 ? b->nbound : 1;
+    for (int i = 0; i < nsets; ++i) {
+        const hipError_t e = hipMemcpyAsync((void *)batch_dtab(b, i), &b->tab[(size_t)i * b->nslab],
+                                            sizeof(BatchEntry) * b->nslab, hipMemcpyHostToDevice, b->st);
+        if (e != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(b->st);
 }
 
 extern "C" int oci_batch_setup(int32_t nslab, const oci_desc *descs, void *workspace_dev, size_t workspace_bytes,
@@ -696,11 +840,16 @@ extern "C" int oci_batch_setup(int32_t nslab, const oci_desc *descs, void *works
     if (!b) return OCI_ERR_HIP;
     b->nslab = nslab;
     b->fp32 = descs[0].precision == OCI_FP32_REFINED;
+    b->structured = descs[0].solver == OCI_SOLVE_STRUCTURED;
     b->st = (hipStream_t)stream;
     b->d_tab = (BatchEntry *)workspace_dev;
+    b->tstride = batch_table_bytes(nslab);
+    b->nbound = 0;
+    b->cursor = 0;
+    b->last = -1;
     b->graph = nullptr;
     unsigned char *ws = (unsigned char *)workspace_dev;
-    size_t off = batch_table_bytes(nslab);
+    size_t off = (size_t)kMaxBatchSteps * batch_table_bytes(nslab);
     for (int k = 0; k < nslab; ++k) {
         size_t bk = 0;
         oci_workspace_bytes(&descs[k], &bk);
@@ -711,7 +860,8 @@ extern "C" int oci_batch_setup(int32_t nslab, const oci_desc *descs, void *works
         off += align256(bk);
     }
     int occ = 0;
-    if (batch_occupancy(b->fp32, &occ) != hipSuccess || occ < 1) { oci_batch_destroy(b); return OCI_ERR_HIP; }
+    const hipError_t oe = b->structured ? wb_batch_occupancy(&occ) : batch_occupancy(b->fp32, &occ);
+    if (oe != hipSuccess || occ < 1) { oci_batch_destroy(b); return OCI_ERR_HIP; }
     b->occ = occ;
     b->tab.resize(nslab);
     for (int k = 0; k < nslab; ++k) {
@@ -721,51 +871,72 @@ extern "C" int oci_batch_setup(int32_t nslab, const oci_desc *descs, void *works
     std::vector<double> wgt(nslab);
     for (int k = 0; k < nslab; ++k) {
         const oci_handle *h = b->slabs[k];
-        wgt[k] = (double)h->d.J * h->np * h->np;     // factor bytes per iteration
+        // bytes per iteration: the factor stream, or for the structured solve
+        // the per-(g, m) sources and edges and the per-cell capacitance rows
+        wgt[k] = b->structured ? (double)h->d.J * (64.0 * h->d.N * h->d.G + 128.0 * h->d.G * h->d.G)
+                               : (double)h->d.J * h->np * h->np;
     }
     rc = batch_allocate(b, wgt);
     if (rc) { oci_batch_destroy(b); return rc; }
-    b->bound = false;
     *out = b;
+    return OCI_OK;
+}
+
+extern "C" int oci_batch_bind_steps(oci_batch *b, int32_t n_steps, const double *const *q_dev,
+                                    const double *const *inc_left_dev, const double *const *inc_right_dev,
+                                    double *const *phi_out_dev, oci_step_info *info_dev) {
+    if (!b || n_steps < 1 || n_steps > kMaxBatchSteps || !phi_out_dev || !info_dev) return OCI_ERR_INVALID;
+    const int ns = b->nslab;
+    for (size_t i = 0; i < (size_t)n_steps * ns; ++i)
+        if (!phi_out_dev[i]) return OCI_ERR_INVALID;
+    // every argument set starts as a copy of set 0's slab views and geometry
+    std::vector<BatchEntry> tab((size_t)n_steps * ns);
+    for (int i = 0; i < n_steps; ++i)
+        for (int k = 0; k < ns; ++k) {
+            BatchEntry &e = tab[(size_t)i * ns + k];
+            e = b->tab[k];
+            const size_t a = (size_t)i * ns + k;
+            StepIO &io = e.io;
+            memset(&io, 0, sizeof(StepIO));
+            io.q = q_dev ? q_dev[a] : nullptr;
+            io.inc_l = inc_left_dev ? inc_left_dev[a] : nullptr;
+            io.inc_r = inc_right_dev ? inc_right_dev[a] : nullptr;
+            io.phi_out = phi_out_dev[a];
+            io.psi_out = nullptr;
+            io.info = info_dev + a;
+        }
+    if (b->graph) { (void)hipGraphExecDestroy(b->graph); b->graph = nullptr; }
+    b->tab.swap(tab);
+    b->nbound = n_steps;
+    b->cursor = 0;
+    b->last = -1;
+    b->info_dev = info_dev;
+    HIPCHECK(batch_upload(b));
     return OCI_OK;
 }
 
 extern "C" int oci_batch_bind(oci_batch *b, const double *const *q_dev, const double *const *inc_left_dev,
                               const double *const *inc_right_dev, double *const *phi_out_dev,
                               oci_step_info *info_dev) {
-    if (!b || !phi_out_dev || !info_dev) return OCI_ERR_INVALID;
-    for (int k = 0; k < b->nslab; ++k) {
-        if (!phi_out_dev[k]) return OCI_ERR_INVALID;
-        StepIO &io = b->tab[k].io;
-        io.q = q_dev ? q_dev[k] : nullptr;
-        io.inc_l = inc_left_dev ? inc_left_dev[k] : nullptr;
-        io.inc_r = inc_right_dev ? inc_right_dev[k] : nullptr;
-        io.phi_out = phi_out_dev[k];
-        io.psi_out = nullptr;
-        io.info = info_dev + k;
-    }
-    b->info_dev = info_dev;
-    if (hipMemcpyAsync(b->d_tab, b->tab.data(), sizeof(BatchEntry) * b->nslab, hipMemcpyHostToDevice, b->st) !=
-        hipSuccess)
-        return OCI_ERR_HIP;
-    if (hipStreamSynchronize(b->st) != hipSuccess) return OCI_ERR_HIP;
-    b->bound = true;
-    return OCI_OK;
+    return oci_batch_bind_steps(b, 1, q_dev, inc_left_dev, inc_right_dev, phi_out_dev, info_dev);
 }
 
 extern "C" int oci_batch_step(oci_batch *b) {
-    if (!b || !b->bound) return OCI_ERR_INVALID;
-    HIPCHECK(launch_batch_step(b->d_tab, b->nslab, b->nwg, b->fp32, false, b->st, true));
+    if (!b || b->nbound < 1) return OCI_ERR_INVALID;
+    HIPCHECK(launch_batch_step(batch_dtab(b, b->cursor), b->nslab, b->nwg, b->fp32, b->structured, false, b->st, true));
+    b->last = b->cursor;
+    b->cursor = (b->cursor + 1) % b->nbound;
     return OCI_OK;
 }
 
 extern "C" int oci_batch_capture(oci_batch *b, int32_t n_steps) {
-    if (!b || !b->bound || n_steps < 1 || !b->st) return OCI_ERR_INVALID;
+    if (!b || b->nbound < 1 || n_steps < 1 || !b->st) return OCI_ERR_INVALID;
     if (b->graph) { (void)hipGraphExecDestroy(b->graph); b->graph = nullptr; }
     HIPCHECK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int k = 0; k < n_steps && e == hipSuccess; ++k)
-        e = launch_batch_step(b->d_tab, b->nslab, b->nwg, b->fp32, false, b->st, false);
+        e = launch_batch_step(batch_dtab(b, (b->cursor + k) % b->nbound), b->nslab, b->nwg, b->fp32, b->structured,
+                              false, b->st, false);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->st, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -776,12 +947,14 @@ extern "C" int oci_batch_capture(oci_batch *b, int32_t n_steps) {
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) { b->graph = nullptr; return OCI_ERR_HIP; }
     b->graph_steps = n_steps;
+    b->graph_first = b->cursor;
     return OCI_OK;
 }
 
 extern "C" int oci_batch_replay(oci_batch *b) {
     if (!b || !b->graph) return OCI_ERR_INVALID;
     HIPCHECK(hipGraphLaunch(b->graph, b->st));
+    b->last = (b->graph_first + b->graph_steps - 1) % b->nbound;
     return OCI_OK;
 }
 
@@ -800,19 +973,21 @@ extern "C" int oci_batch_get_state(const oci_batch *b, int32_t k, double *psi_pr
 }
 
 extern "C" int oci_batch_rebalance(oci_batch *b) {
-    if (!b || !b->bound) return OCI_ERR_INVALID;
+    if (!b || b->nbound < 1 || b->last < 0) return OCI_ERR_INVALID;
     std::vector<oci_step_info> info(b->nslab);
     HIPCHECK(hipStreamSynchronize(b->st));
-    HIPCHECK(hipMemcpy(info.data(), b->info_dev, sizeof(oci_step_info) * b->nslab, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(info.data(), b->info_dev + (size_t)b->last * b->nslab, sizeof(oci_step_info) * b->nslab,
+                       hipMemcpyDeviceToHost));
     std::vector<double> wgt(b->nslab);
     for (int k = 0; k < b->nslab; ++k) {
         const oci_handle *h = b->slabs[k];
         const int its = info[k].iterations > 0 ? info[k].iterations : 1;
-        wgt[k] = (double)h->d.J * h->np * h->np * its;
+        wgt[k] = (b->structured ? (double)h->d.J * (64.0 * h->d.N * h->d.G + 128.0 * h->d.G * h->d.G)
+                                : (double)h->d.J * h->np * h->np) * its;
     }
     const int rc = batch_allocate(b, wgt);
     if (rc) return rc;
-    HIPCHECK(hipMemcpy(b->d_tab, b->tab.data(), sizeof(BatchEntry) * b->nslab, hipMemcpyHostToDevice));
+    HIPCHECK(batch_upload(b));
     if (b->graph) { (void)hipGraphExecDestroy(b->graph); b->graph = nullptr; }
     return OCI_OK;
 }
@@ -835,7 +1010,7 @@ extern "C" const char *oci_status_string(int s) {
     case OCI_ERR_SINGULAR: return "singular cell matrix (zero pivot)";
     case OCI_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
     case OCI_ERR_UNSUPPORTED: return "cell system larger than the compiled kernels (4 N G > 512)";
-    case OCI_ERR_DEVICE: return "device guard tripped (grid barrier did not complete)";
+    case OCI_ERR_DEVICE: return "device-side wait expired (a workgroup of the persistent launch was not co-resident)";
     default: return "unknown status";
     }
 }

@@ -81,6 +81,15 @@ struct Slab {
     double *si_alpha;            // [J][NG][2] outgoing edges of the uncoupled solution, sweep order
     double *si_ein;              // [J][NG][2] incident edges met by the sweep, sweep order
     double *partials;            // [kPartSlots][max workgroups] per-workgroup sums (by iteration mod 2, or mod kPartSlots)
+    int32_t zero_cell;           // test hook: the setup zeroes column 0 of this cell's matrix (-1: none)
+    int32_t ordering;            // 0: Jacobi over cells, 1: red-black (structured solve)
+    int32_t periodic;            // 1: periodic mesh instead of incident fluxes (structured solve)
+    int32_t hist_cap;            // entries of hist
+    double *hist;                // e_l of every iteration of the last step, or null
+    double *edge;                // structured solve: [2][J][G][N][2] outgoing corners of each (g, m) at
+                                 // levels k and k+1/2, by iteration parity
+    double *wb;                  // structured cell solve: [J][4G][2G] complex, the rows of (I - W C)^-1 then of
+                                 // C (I - W C)^-1 (see oci_wb.hip); null for the dense solve
     Ctl *ctl;
     // grid barrier words, 256 bytes apart: [0] arrivals of group leaders,
     // [kBarStride] release flag, [(2 + k) * kBarStride] arrivals in group k
@@ -102,6 +111,9 @@ struct StepIO {
     void *info;                  // oci_step_info*
     int32_t nsteps;              // time steps in one launch (register-resident kernel; <= 1: one);
                                  // phi_out and info then hold one record per step
+    int32_t pad;
+    int64_t q_stride;            // elements between consecutive steps' q (0: the same q every step)
+    int64_t inc_stride;          // elements between consecutive steps' inc_l / inc_r (0: the same)
 };
 
 // One slab of a batch: its view, its step inputs/outputs, and the block of

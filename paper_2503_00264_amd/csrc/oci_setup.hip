@@ -40,6 +40,7 @@ struct TiledMat {
 // Value of A_j at (r, c) (double precision).  Unknown index (g*N + m)*4 + u.
 __device__ inline double cell_entry(const Slab &S, int j, int r, int c) {
     if (r >= S.n || c >= S.n) return r == c ? 1.0 : 0.0;  // padding block: identity
+    if (j == S.zero_cell && c == 0) return 0.0;            // test hook: a zero pivot
     const int N = S.N, G = S.G;
     const int gr = r / (4 * N), mr = (r / 4) % N, ur = r & 3;
     const int gc = c / (4 * N), mc = (c / 4) % N, uc = c & 3;
@@ -364,6 +365,7 @@ __device__ void assemble_tiled(const Slab &S, int j, T *X, double *cw) {
                     if (diag) x += Lr[uc];
                     v[uc] = (T)x;
                 }
+                if (blk == 0 && j == S.zero_cell) v[0] = T(0);   // test hook: a zero pivot
             }
             for (int w = 0; w < 4 / V; ++w) copy16(X + ((size_t)(blk * (4 / V) + w) * np + r) * V, v + w * V);
             if (++mc == N) { mc = 0; ++gc; }
@@ -686,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void k_si_invert(Slab S) {
 hipError_t launch_setup(const Slab &S, bool fp32, hipStream_t st) {
     const int n = S.np;
     const int chunk = 65535;
-    for (int j0 = 0; j0 < S.J; j0 += chunk) {
+    for (int j0 = 0; j0 < (S.wb ? 0 : S.J); j0 += chunk) {   // no n x n factors for the structured solve
         const int nb = (S.J - j0) < chunk ? (S.J - j0) : chunk;
         hipError_t e;
         if (n <= 64) {

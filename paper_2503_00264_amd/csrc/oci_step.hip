@@ -23,30 +23,9 @@
 // SI (Appendix A, Algorithm 1): one kernel sweeps all (group, angle) chains
 // cell by cell with the lagged scattering source, a second forms phi and the
 // norm and takes the decision (last-block reduction).
-#include "oci_internal.hpp"
+#include "oci_device.hpp"
 
 namespace oci {
-
-constexpr int OK = 0, NOT_CONVERGED = 1, NONFINITE = 2;
-
-// --------------------------------------------------------------- reductions
-__device__ inline double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Fixed-shape workgroup sum (same pairing every call, so deterministic).
-__device__ inline double block_sum(double v, double *s_tmp) {
-    v = wave_sum(v);
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) s_tmp[wave] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kBlock / 64; ++w) t += s_tmp[w];
-    __syncthreads();
-    return t;  // valid in thread 0
-}
 
 // Stopping rule of section 2.1 / Algorithms 1-2 applied to the new change e.
 __device__ inline void decide(const Slab &S, double e) {
@@ -137,10 +116,14 @@ __global__ __launch_bounds__(kBlock) void k_step_open(Slab S, StepIO io, int nwg
 __device__ inline void broadcast_elem(const Slab &S, size_t t) {
     S.psi[S.ctl->base][t] = S.psi_prev[(t >> 2) * 2 + (t & 1)];
 }
-__global__ __launch_bounds__(kBlock) void k_broadcast_state(Slab S) {
+// from_flag: only when the control block's broadcast flag is set (steps
+// captured in a graph learn on the device whether the state was replaced).
+__global__ __launch_bounds__(kBlock) void k_broadcast_state(Slab S, int from_flag) {
+    if (from_flag && !S.ctl->bcast) return;
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < (size_t)S.J * S.G * S.N * 4) broadcast_elem(S, t);
 }
+__global__ void k_clear_bcast(Slab S) { S.ctl->bcast = 0; }
 
 // After a step: time update psi_{k-1/2} <- psi_{k+1/2} and the outputs.
 // Elements: one per (j, g, m) row quad and per phi entry.
@@ -224,73 +207,6 @@ __device__ inline void stream_rows(const T *Xc, int t, const T *vec, T (&acc)[RP
             for (int r = 0; r < RPT; ++r) acc[r] += dot16(xv[u][r], bv);
         }
     }
-}
-
-template <int BS>
-__device__ inline double block_sum_t(double v, double *s_tmp) {
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) s_tmp[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < BS / 64; ++w) t += s_tmp[w];
-    __syncthreads();
-    return t;  // valid in thread 0
-}
-
-// Grid barrier over the co-resident workgroups of one launch, once per
-// iteration l, fused with the reduction of the per-workgroup sums.
-// Counters only grow during a step (they are reset before it), so barrier l
-// has a known target and nobody reads shared state to learn it: workgroups
-// arrive at their group's counter, the last of a group arrives at the top
-// counter, and everybody waits for the top counter to reach (l + 1) x groups.
-// Arrivals are agent-scope acquire-release read-modify-writes (publishing the
-// workgroup's stores, its partial sum included); the wait uses relaxed loads
-// and one agent-scope acquire at the end, so no cache maintenance happens
-// inside the spin.  Then every workgroup sums the partials of iteration l in
-// the same fixed order, so all of them hold the identical total and take the
-// identical stopping decision with no second round trip.  The spin is
-// bounded: on expiry the control block's err flag is raised and the caller
-// leaves its loop, so the grid always drains.
-constexpr long kSpinLimit = 1L << 25;
-
-template <int BS>
-__device__ inline bool grid_sync_sum(const Slab &S, unsigned wg, unsigned nwg, int l, double wg_sum, int *s_flag,
-                                     double *s_tmp, double *total) {
-    double *part = S.partials + (size_t)(l & 1) * nwg;
-    if (threadIdx.x == 0) part[wg] = wg_sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned gsz_all = (unsigned)S.bar_gsz;
-        const unsigned grp = wg / gsz_all;
-        const unsigned ngrp = (nwg + gsz_all - 1) / gsz_all;
-        const unsigned gsz = (grp + 1 == ngrp) ? nwg - grp * gsz_all : gsz_all;
-        const uint64_t round = (uint64_t)l + 1;
-        uint64_t *gc = S.bar + (size_t)(2 + grp) * kBarStride;
-        const uint64_t og = __hip_atomic_fetch_add(gc, (uint64_t)1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (og + 1 == round * gsz)
-            (void)__hip_atomic_fetch_add(S.bar, (uint64_t)1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        int bad = 0;
-        long spins = 0;
-        while (__hip_atomic_load(S.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round * ngrp) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) {
-                __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                bad = 1;
-                break;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        s_flag[2] = bad;
-    }
-    __syncthreads();
-    double v = 0.0;
-    for (unsigned k = threadIdx.x; k < nwg; k += BS) v += part[k];
-    v = block_sum_t<BS>(v, s_tmp);
-    if (threadIdx.x == 0) s_tmp[BS / 64] = v;
-    __syncthreads();
-    *total = s_tmp[BS / 64];
-    return s_flag[2] == 0;
 }
 
 // Coefficients of row u of the 4x4 corner block L_{c,j,g,m} (eq. Aj) acting
@@ -557,6 +473,7 @@ __device__ __attribute__((always_inline)) inline void oci_global_body(const Slab
         else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - e / e_prev))) done = 1;
         else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
         e_prev = e;
+        if (S.hist && iters <= S.hist_cap && wg == 0 && tid == 0) S.hist[iters - 1] = e;
         if (done) {
             if (wg == 0 && tid == 0) {
                 Ctl *c = S.ctl;
@@ -678,14 +595,6 @@ __device__ inline int seg_max_i32(int v) {
     return v;
 }
 
-// Orders the LDS accesses of one wave before and after it (the wave's LDS
-// operations complete in issue order; this only keeps the compiler from
-// moving them across).
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Workgroup-local persistent OCI kernel with streamed inverse rows.  Each
 // workgroup owns the contiguous cells [c0, c1) (one or more tiles) for the
@@ -832,6 +741,7 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
             else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - rho))) done = 1;
             else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
             e_prev = e;
+            if (S.hist && iters <= S.hist_cap && wg == 0 && lane == 0) S.hist[iters - 1] = e;
             if (lane == 0) {
                 s_dec[l & 1][0] = done;
                 s_dec[l & 1][1] = status;
@@ -1142,10 +1052,14 @@ __device__ __attribute__((always_inline)) inline void res_next_step(const Slab &
         const int j = c0 + cl;
         const double mu = mu_tab[m], dx = S.dx[j];
         const size_t jg = (size_t)j * G + g;
-        double c = io.q ? 0.25 * dx * io.q[jg * 4 + u] : 0.0;
+        // the next step's sources (per-step arrays when the strides are set)
+        const double *q = io.q ? io.q + (size_t)(step + 1) * io.q_stride : nullptr;
+        const double *il = io.inc_l ? io.inc_l + (size_t)(step + 1) * io.inc_stride : nullptr;
+        const double *ir = io.inc_r ? io.inc_r + (size_t)(step + 1) * io.inc_stride : nullptr;
+        double c = q ? 0.25 * dx * q[jg * 4 + u] : 0.0;
         if (u < 2) c += dx / (2.0 * S.speed[g] * S.dt) * Q_psi[(size_t)cl * n + t + 2];
-        if ((ri & res::INL) && (ri & res::BND) && io.inc_l) c += mu * io.inc_l[((size_t)lev * G + g) * nh + (m - nh)];
-        if ((ri & res::INR) && (ri & res::BND) && io.inc_r) c -= mu * io.inc_r[((size_t)lev * G + g) * nh + m];
+        if ((ri & res::INL) && (ri & res::BND) && il) c += mu * il[((size_t)lev * G + g) * nh + (m - nh)];
+        if ((ri & res::INR) && (ri & res::BND) && ir) c -= mu * ir[((size_t)lev * G + g) * nh + m];
         crow[(size_t)cl * ldc + t] = c;
         const double x = Q_psi[(size_t)cl * n + t];
         uint64_t *ex = reinterpret_cast<uint64_t *>(S.exch);
@@ -1513,6 +1427,7 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
             else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
             else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - rho))) done = 1;
             else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
+            if (S.hist && iters <= S.hist_cap && wg == 0 && (tid & 63) == 0) S.hist[iters - 1] = e;
             if ((tid & 63) == 0) {
                 s_eprev[l & 1] = e;
                 s_dec[l & 1][0] = done;
@@ -1763,7 +1678,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_elems(const BatchEntry *tab, i
     if (what == 0) {           // first iterate (when the state was replaced) and the constant RHS
         if (broadcast || S.ctl->bcast)
             for (size_t t = t0; t < (size_t)S.J * S.n; t += stride) broadcast_elem(S, t);
-        for (size_t t = t0; t < (size_t)S.J * S.n; t += stride) const_rhs_elem(S, e.io, t);
+        if (!S.wb)
+            for (size_t t = t0; t < (size_t)S.J * S.n; t += stride) const_rhs_elem(S, e.io, t);
     } else if (what == 1) {    // phi of the first iterate
         for (size_t t = t0; t < (size_t)S.J * S.G * 4; t += stride) phi0_elem(S, t);
         if (t0 == 0) S.ctl->bcast = 0;
@@ -1803,15 +1719,18 @@ hipError_t launch_flag_broadcast(const Slab &S, hipStream_t st) {
 // One batched time step: bookkeeping for all slabs, the persistent launch,
 // the end-of-step kernel.  No memset and no host synchronisation, so the
 // sequence can be captured into a graph (then with a normal launch).
-hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp32, bool broadcast, hipStream_t st,
-                             bool coop) {
+hipError_t launch_wb_batch(const BatchEntry *tab, int nslab, int nwg, hipStream_t st);
+
+hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp32, bool structured, bool broadcast,
+                             hipStream_t st, bool coop) {
     hipLaunchKernelGGL(k_batch_begin, dim3(nslab), dim3(1), 0, st, tab);
     hipLaunchKernelGGL(k_batch_elems, dim3(256, nslab), dim3(kBlock), 0, st, tab, 0, broadcast ? 1 : 0);
     hipLaunchKernelGGL(k_batch_elems, dim3(64, nslab), dim3(kBlock), 0, st, tab, 1, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = fp32 ? batch_launch_t<float, kBatchBlock>(tab, nslab, nwg, st, coop)
-             : batch_launch_t<double, kBatchBlock>(tab, nslab, nwg, st, coop);
+    e = structured ? launch_wb_batch(tab, nslab, nwg, st)
+        : fp32     ? batch_launch_t<float, kBatchBlock>(tab, nslab, nwg, st, coop)
+                   : batch_launch_t<double, kBatchBlock>(tab, nslab, nwg, st, coop);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_elems, dim3(256, nslab), dim3(kBlock), 0, st, tab, 2, 0);
     return hipGetLastError();
@@ -1970,20 +1889,24 @@ hipError_t launch_oci_local(const Slab &S, const StepIO &io, bool fp32, int np, 
     return dispatch(fp32, np, res, bs, LaunchLocalF{S, io, nwg, ntiles, dyn, st});
 }
 
-hipError_t launch_begin(const Slab &S, const StepIO &io, bool broadcast_state, hipStream_t st, int local_nwg) {
+// broadcast: 0 = continue from the last iterate, 1 = start from the state
+// on both time levels, 2 = decide on the device (the control block's flag).
+hipError_t launch_begin(const Slab &S, const StepIO &io, int broadcast, hipStream_t st, int local_nwg) {
     hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, st, S);
-    {
+    if (!S.wb) {   // the structured solve forms the constant part of b itself
         const size_t tot = (size_t)S.J * S.n;
         hipLaunchKernelGGL(k_const_rhs, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S, io);
     }
-    if (broadcast_state) {
+    if (broadcast) {
         const size_t tot = (size_t)S.J * S.G * S.N * 4;
-        hipLaunchKernelGGL(k_broadcast_state, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S);
+        hipLaunchKernelGGL(k_broadcast_state, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S,
+                           broadcast == 2 ? 1 : 0);
     }
     size_t tot = (size_t)S.J * S.G * 4;
     const size_t nex = (size_t)8 * local_nwg * S.N * S.G;
     if (nex > tot) tot = nex;
     hipLaunchKernelGGL(k_phi0, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S, local_nwg);
+    if (broadcast == 2) hipLaunchKernelGGL(k_clear_bcast, dim3(1), dim3(1), 0, st, S);
     return hipGetLastError();
 }
 

@@ -100,8 +100,10 @@ def test_step_calls_reject_null_handle_and_outputs():
     L = B.lib()
     assert L.oci_step(None, None, None, None, None, None, None) == B.OCI_ERR_INVALID
     assert L.si_step(None, None, None, None, None, None, None) == B.OCI_ERR_INVALID
-    assert L.oci_run_steps(None, 3, None, None, None, None, None, None) == B.OCI_ERR_INVALID
-    assert L.oci_run_steps(None, 0, None, None, None, None, None, None) == B.OCI_ERR_INVALID
+    assert L.oci_run_steps(None, 3, None, 0, None, None, 0, None, None, None) == B.OCI_ERR_INVALID
+    assert L.oci_run_steps(None, 0, None, 0, None, None, 0, None, None, None) == B.OCI_ERR_INVALID
+    assert L.oci_capture_steps(None, 2, None, None, None, None, None, None) == B.OCI_ERR_INVALID
+    assert L.oci_replay_steps(None) == B.OCI_ERR_INVALID
     assert L.oci_set_state(None, None) == B.OCI_ERR_INVALID
     assert L.oci_get_state(None, None) == B.OCI_ERR_INVALID
     assert L.oci_destroy(None) == B.OCI_ERR_INVALID
@@ -122,3 +124,28 @@ def test_product_code_does_not_reference_the_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), os.path.join(dirpath, f)
+
+
+@pytest.mark.parametrize("over", [dict(solver=2), dict(solver=-1)])
+def test_unknown_solver_rejected(over):
+    d, keep = _desc(**over)
+    n = C.c_size_t(0)
+    assert B.lib().oci_workspace_bytes(C.byref(d), C.byref(n)) == B.OCI_ERR_INVALID
+
+
+@pytest.mark.parametrize("over", [dict(precision=B.OCI_FP32_REFINED), dict(norm=B.OCI_NORM_ANGULAR)])
+def test_structured_solve_options_unsupported(over):
+    d, keep = _desc(solver=B.OCI_SOLVE_STRUCTURED, **over)
+    n = C.c_size_t(0)
+    assert B.lib().oci_workspace_bytes(C.byref(d), C.byref(n)) == B.OCI_ERR_UNSUPPORTED
+
+
+def test_structured_workspace_holds_no_dense_factors():
+    p = W.multigroup(seed=3, J=64, N=16, G=4, n_regions=8, length=1.0, dt=1e-3)
+    dense, k1 = B.make_desc(p)
+    struct, k2 = B.make_desc(p, solver=B.OCI_SOLVE_STRUCTURED)
+    nd, ns = B.oci_workspace_bytes(dense), B.oci_workspace_bytes(struct)
+    # the dense form stores 64 cells x 256^2 FP64 words; the structured form
+    # 64 cells x 16 G^2 words of capacitance rows and a double-buffered
+    # [J][G][N][2] array of outgoing corners instead
+    assert nd - ns == 64 * 256 * 256 * 8 - (64 * 16 * 16 * 8 + 2 * 64 * 64 * 2 * 8)

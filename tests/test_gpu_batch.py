@@ -131,3 +131,67 @@ def test_batch_rebalance_keeps_results():
     assert all(i["iterations"] == 5 for i in ib)
     for k in range(len(probs)):
         assert rel(pb[k], pa[k]) <= 1e-12, (k, before, after)
+
+
+# ------------------------------------------------------ structured batches
+def test_structured_batch_lockstep_matches_oracle_per_slab():
+    probs = [p for p in small_batch(seed=11) if p["G"] <= 8]
+    _announce(probs, "structured fp64 lock-step K=5, 2 steps")
+    bs = B.BatchSolver(probs, precision=B.OCI_FP64, fixed_iters=5, solver=B.OCI_SOLVE_STRUCTURED)
+    got = []
+    for _ in range(2):
+        bs.step()
+        phis, infos = bs.results()
+        got.append(phis)
+        assert all(i["iterations"] == 5 and i["status"] == 0 for i in infos), infos
+    bs.close()
+    for k, p in enumerate(probs):
+        want = oracle.Oracle(p).run("oci", steps=2, fixed_iters=5)["phi"]
+        for s in range(2):
+            assert rel(got[s][k], want[s]) <= 1e-12, (k, s)
+
+
+def test_structured_batch_converges_and_replays():
+    """Converged structured batch steps (graph of 2 steps, replayed twice)
+    against the oracle's converged truth per slab, and the replays against
+    eager batched steps bit for bit."""
+    probs = [p for p in small_batch(seed=12) if p["G"] <= 8]
+    _announce(probs, "structured converged, graph of 2 steps vs eager vs oracle")
+    g = B.BatchSolver(probs, precision=B.OCI_FP64, tol=1e-12, solver=B.OCI_SOLVE_STRUCTURED)
+    e = B.BatchSolver(probs, precision=B.OCI_FP64, tol=1e-12, solver=B.OCI_SOLVE_STRUCTURED)
+    g.capture(2)
+    for r in range(2):
+        g.replay()
+        pg, ig = g.results()
+        e.step()
+        e.step()
+        pe, ie = e.results()
+        for k in range(len(probs)):
+            assert np.array_equal(pg[k], pe[k]), (r, k)
+            assert ig[k] == ie[k], (r, k)
+    g.close()
+    e.close()
+    for k, p in enumerate(probs):
+        want = oracle.Oracle(p).run("oci", steps=4, tol=1e-14)["phi"][-1]
+        assert rel(pg[k], want) <= 1e-10, k
+
+
+def test_batch_per_step_argument_sets():
+    """Bound per-step argument sets: a graph of 3 steps writes each step's
+    flux and report into its own set, equal to eager steps one by one."""
+    probs = [p for p in small_batch(seed=13, n_slabs=4) if 4 * p["N"] * p["G"] <= 512]
+    _announce(probs, "per-step argument sets, 3-step graph vs eager")
+    g = B.BatchSolver(probs, precision=B.OCI_FP32_REFINED, tol=1e-10)
+    g.bind_steps(3)
+    g.capture(3)
+    g.replay()
+    pg, ig = g.step_results()
+    g.close()
+    e = B.BatchSolver(probs, precision=B.OCI_FP32_REFINED, tol=1e-10)
+    for i in range(3):
+        e.step()
+        pe, ie = e.results()
+        for k in range(len(probs)):
+            assert np.array_equal(pg[i][k], pe[k]), (i, k)
+            assert ig[i][k] == ie[k], (i, k)
+    e.close()

@@ -15,6 +15,7 @@ Every case prints its name, shape and seed before touching the GPU.
 import numpy as np
 import pytest
 
+import balance as BAL
 import oracle
 from paper_2503_00264_amd import binding as B
 from paper_2503_00264_amd import workloads as W
@@ -274,20 +275,31 @@ def test_state_roundtrip_restart():
 def test_kernel_variants_lockstep(name, mode, monkeypatch):
     """Every launch variant (global-memory kernel, streamed factors, block size,
     barrier arrival groups, several tiles per workgroup) gives the oracle's
-    lock-step answer."""
+    answer: FP64 in lock-step (<= 1e-12), and FP32-refined both in lock-step
+    (iteration counts) and converged on the GPU (tol 1e-12) against the
+    oracle converged to 1e-14 (<= 1e-10)."""
     for k, v in mode.items():
         monkeypatch.setenv(k, v)
     p, steps = CASES[name]
     K = 6
     _announce(name, p, f"variant {mode} K={K}")
-    for prec, tol in ((B.OCI_FP64, 1e-12), (B.OCI_FP32_REFINED, None)):
+    o = oracle.Oracle(p)
+    for prec in (B.OCI_FP64, B.OCI_FP32_REFINED):
         s = B.Solver(p, precision=prec, fixed_iters=K)
         got, infos = s.run(steps=steps)
         s.close()
         assert all(i["iterations"] == K and i["status"] == 0 for i in infos), infos
-        if tol is not None:
-            want = oracle.Oracle(p).run("oci", steps=steps, fixed_iters=K)["phi"]
-            assert rel(got, want) <= tol
+        if prec == B.OCI_FP64:
+            assert rel(got, o.run("oci", steps=steps, fixed_iters=K)["phi"]) <= 1e-12
+    truth = o.run("oci", steps=steps, tol=1e-14)["phi"]
+    s = B.Solver(p, precision=B.OCI_FP32_REFINED, tol=1e-12)
+    cfg = s.config()
+    got, infos = s.run(steps=steps)
+    s.close()
+    assert all(i["status"] == 0 for i in infos), infos
+    err = rel(got, truth)
+    print(f"  refined converged, shape {cfg}: normwise relative error {err:.2e}", flush=True)
+    assert err <= 1e-10
 
 
 @pytest.mark.parametrize("name", ["regions512_n64", "multigroup128_n256", "G3_n48"])
@@ -306,6 +318,16 @@ def test_autotune_keeps_parity(name):
         if prec == B.OCI_FP64:
             want = oracle.Oracle(p).run("oci", steps=steps, fixed_iters=6)["phi"]
             assert rel(got, want) <= 1e-12
+    # the refined path in the tuned shape, converged, against the oracle's
+    # converged truth
+    s = B.Solver(p, precision=B.OCI_FP32_REFINED, tol=1e-12)
+    cfg = s.autotune(iters=4)
+    got, infos = s.run(steps=steps)
+    s.close()
+    assert all(i["status"] == 0 for i in infos), infos
+    err = rel(got, oracle.Oracle(p).run("oci", steps=steps, tol=1e-14)["phi"])
+    print(f"  refined converged in the tuned shape {cfg}: normwise relative error {err:.2e}", flush=True)
+    assert err <= 1e-10
 
 
 def _multi_step_cases():
@@ -411,3 +433,306 @@ def test_run_steps_statuses_equal_single_steps(case):
     assert all(i["status"] == want for i in out[1][1]), out[1][1]
     assert [(i["iterations"], i["status"]) for i in out[0][1]] == [(i["iterations"], i["status"]) for i in out[1][1]]
     assert np.array_equal(out[0][0], out[1][0], equal_nan=True)
+
+
+# ---------------------------------------------------------------- structured
+# The structured exact cell solve (OCI_SOLVE_STRUCTURED): the same OCI
+# iteration with each cell system solved through its block structure (4x4
+# corner blocks inverted in closed form, the rank-4G scattering coupling
+# through a capacitance matrix).  Same bars as the dense FP64 path.
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_structured_fp64_lockstep(name):
+    p, steps = CASES[name]
+    K = 7
+    _announce(name, p, f"structured oci fp64 lock-step K={K} steps={steps}")
+    want = oracle.Oracle(p).run("oci", steps=steps, fixed_iters=K)
+    s = B.Solver(p, precision=B.OCI_FP64, fixed_iters=K, solver=B.OCI_SOLVE_STRUCTURED)
+    got, infos = s.run(steps=steps, want_psi=True)
+    state = s.get_state().cpu().numpy()
+    s.close()
+    assert all(i["iterations"] == K and i["status"] == 0 for i in infos), infos
+    assert rel(got, want["phi"]) <= 1e-12
+    assert rel(state, want["psi_prev"]) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["homogeneous64_n32", "regions512_n64", "multigroup192_n128",
+                                  "multigroup128_n256", "multigroup40_n512", "G3_n48", "G3_N16_n192",
+                                  "rosa_S16_dt0.1"])
+def test_structured_converges_to_oracle(name):
+    p, steps = CASES[name]
+    _announce(name, p, "structured oci converged")
+    # converged answers differ from the fixed point by about tol rho / (1 - rho)
+    # (absolute), so the converged bar is the refined path's 1e-10; the 1e-12
+    # bar of FP64 is the lock-step test above
+    ref = oracle.Oracle(p).run("oci", steps=steps, tol=1e-14)
+    s = B.Solver(p, precision=B.OCI_FP64, tol=1e-12, solver=B.OCI_SOLVE_STRUCTURED)
+    got, infos = s.run(steps=steps)
+    s.close()
+    assert all(i["status"] == 0 for i in infos), infos
+    err = rel(got, ref["phi"])
+    print(f"  normwise relative error {err:.2e}", flush=True)
+    assert err <= 1e-10
+
+
+def test_structured_iteration_counts_match_oracle():
+    p = W.config("homogeneous64")
+    _announce("homogeneous64", p, "structured converged, 10 steps, tol 1e-10: iteration counts")
+    ref = oracle.Oracle(p).run("oci", tol=1e-10)
+    s = B.Solver(p, precision=B.OCI_FP64, tol=1e-10, solver=B.OCI_SOLVE_STRUCTURED)
+    got, infos = s.run()
+    s.close()
+    assert [i["iterations"] for i in infos] == [i["iterations"] for i in ref["info"]]
+    assert rel(got, ref["phi"]) <= 1e-12
+
+
+def test_structured_boundary_sources_and_initial_state():
+    p = W.multigroup(seed=9, J=96, N=8, G=2, n_regions=8, length=2.0, speeds=(3.0, 1.0), dt=0.2,
+                     steps=3)
+    rng = np.random.default_rng(21)
+    p["inc_left"] = rng.uniform(0, 1, size=(2, 2, 4))
+    p["inc_right"] = rng.uniform(0, 1, size=(2, 2, 4))
+    p["psi_init"] = rng.uniform(0, 1, size=(96, 2, 8, 2))
+    _announce("boundary", p, "structured: incident fluxes + initial state")
+    want = oracle.Oracle(p).run("oci", fixed_iters=6)
+    s = B.Solver(p, precision=B.OCI_FP64, fixed_iters=6, solver=B.OCI_SOLVE_STRUCTURED)
+    got, _ = s.run(want_psi=True)
+    psi = s.psi.cpu().numpy()
+    state = s.get_state().cpu().numpy()
+    s.close()
+    assert rel(got, want["phi"]) <= 1e-12
+    assert rel(state, want["psi_prev"]) <= 1e-12
+    assert rel(psi, want["psi_iter"]) <= 1e-12
+
+
+@pytest.mark.parametrize("override", [{}, {"OCI_MAX_WG": "3"}, {"OCI_BAR_GROUP": "3"}])
+def test_structured_run_steps_and_launch_shapes(override, monkeypatch):
+    """Several workgroups' worth of tiles per workgroup, other barrier arrival
+    groups and oci_run_steps all give the single-step answer bit for bit."""
+    for k, v in override.items():
+        monkeypatch.setenv(k, v)
+    p = dict(CASES["regions512_n64"][0], steps=4)
+    _announce("regions512_n64", p, f"structured, {override}")
+    a = B.Solver(p, precision=B.OCI_FP64, tol=1e-11, solver=B.OCI_SOLVE_STRUCTURED)
+    want, winfo = a.run()
+    a.close()
+    b = B.Solver(p, precision=B.OCI_FP64, tol=1e-11, solver=B.OCI_SOLVE_STRUCTURED)
+    got, ginfo = b.run_steps()
+    b.close()
+    assert ginfo == winfo
+    assert np.array_equal(got, want)
+    ref = oracle.Oracle(p).run("oci", tol=1e-14)["phi"]
+    assert rel(got, ref) <= 1e-10
+
+
+def test_structured_rejects_unsupported_options():
+    p = W.homogeneous(J=16, N=4)
+    for kw in (dict(precision=B.OCI_FP32_REFINED), dict(norm=B.OCI_NORM_ANGULAR)):
+        with pytest.raises(B.OciError) as e:
+            B.Solver(p, solver=B.OCI_SOLVE_STRUCTURED, **kw)
+        assert e.value.code == B.OCI_ERR_UNSUPPORTED
+
+
+# ------------------------------------------------- time-dependent sources
+def _time_dependent(steps=4):
+    """A problem whose source and incident fluxes change every step."""
+    p = W.multigroup(seed=9, J=96, N=8, G=2, n_regions=8, length=2.0, speeds=(3.0, 1.0), dt=0.2,
+                     steps=steps)
+    rng = np.random.default_rng(41)
+    qs = [rng.uniform(0, 2, size=(96, 2, 4)) for _ in range(steps)]
+    ls = [rng.uniform(0, 1, size=(2, 2, 4)) for _ in range(steps)]
+    rs = [rng.uniform(0, 1, size=(2, 2, 4)) for _ in range(steps)]
+    return p, qs, ls, rs
+
+
+def _oracle_time_dependent(p, qs, ls, rs, **kw):
+    o = oracle.Oracle(p)
+    pp, pi = o.initial_state()
+    out = []
+    for q, l, r in zip(qs, ls, rs):
+        phi, _ = o.step("oci", pp, pi, q=q, inc_l=l, inc_r=r, **kw)
+        out.append(phi)
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("prec,solver", [(B.OCI_FP64, B.OCI_SOLVE_DENSE), (B.OCI_FP32_REFINED, B.OCI_SOLVE_DENSE),
+                                         (B.OCI_FP64, B.OCI_SOLVE_STRUCTURED)])
+def test_capture_steps_time_dependent_sources(prec, solver):
+    """Steps captured into a graph with per-step sources and incident fluxes
+    equal eager oci_step calls bit for bit (two replays in a row, the second
+    continuing from the first), and the oracle's lock-step answer (FP64)."""
+    p, qs, ls, rs = _time_dependent()
+    K = len(qs)
+    _announce("time_dependent", p, f"capture {K} steps, prec={prec}, solver={solver}")
+    dev = lambda a: torch.as_tensor(a).cuda()
+    dq, dl, dr = [dev(x) for x in qs], [dev(x) for x in ls], [dev(x) for x in rs]
+    torch.cuda.synchronize()
+    kw = dict(precision=prec, solver=solver, fixed_iters=6)
+    e = B.Solver(p, **kw)     # eager steps on torch's current stream, where the clones run
+    want = []
+    for rep in range(2):
+        for k in range(K):
+            B.oci_step(e.h, dq[k], dl[k], dr[k], e.phi, None, e.info)
+            want.append(e.phi.clone())
+    e.stream.synchronize()
+    e.close()
+    s = B.Solver(p, stream=torch.cuda.Stream(), **kw)
+    phis = [torch.zeros_like(s.phi) for _ in range(K)]
+    infos = torch.zeros(24 * K, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    B.oci_capture_steps(s.h, K, dq, dl, dr, phis, None, infos)
+    got = []
+    for rep in range(2):
+        B.oci_replay_steps(s.h)
+        s.stream.synchronize()
+        got += [f.clone() for f in phis]
+        inf = infos.cpu().numpy()
+        assert all(B.decode_info(inf[24 * k:24 * k + 24])["iterations"] == 6 for k in range(K))
+    s.close()
+    for a, b in zip(got, want):
+        assert torch.equal(a, b)
+    if prec == B.OCI_FP64:
+        ref = _oracle_time_dependent(p, qs, ls, rs, fixed_iters=6)
+        assert rel(torch.stack(got[:K]).cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [B.OCI_FP64, B.OCI_FP32_REFINED])
+def test_run_steps_strided_sources(prec):
+    """oci_run_steps with one source and incident-flux array per step (the
+    register-resident kernel turns each step over with the next step's
+    arrays) equals one oci_step call per step bit for bit."""
+    p, qs, ls, rs = _time_dependent(steps=5)
+    K = len(qs)
+    _announce("time_dependent", p, f"oci_run_steps with strides, prec={prec}")
+    qa = torch.as_tensor(np.stack(qs)).cuda()
+    la = torch.as_tensor(np.stack(ls)).cuda()
+    ra = torch.as_tensor(np.stack(rs)).cuda()
+    torch.cuda.synchronize()
+    e = B.Solver(p, precision=prec, tol=1e-10)
+    want, winfo = [], []
+    for k in range(K):
+        B.oci_step(e.h, qa[k], la[k], ra[k], e.phi, None, e.info)
+        want.append(e.phi.clone())
+        winfo.append(e.info.clone())
+    e.stream.synchronize()
+    e.close()
+    s = B.Solver(p, precision=prec, tol=1e-10)
+    resident = s.config()["resident"]
+    phis = torch.empty((K,) + tuple(s.phi.shape), dtype=torch.float64, device="cuda")
+    infos = torch.zeros((K, 24), dtype=torch.uint8, device="cuda")
+    B.oci_run_steps(s.h, K, qa, la, ra, phis, None, infos, q_stride=qa[0].numel(), inc_stride=la[0].numel())
+    s.stream.synchronize()
+    s.close()
+    if prec == B.OCI_FP32_REFINED:
+        assert resident, "the multi-step launch needs the register-resident kernel here"
+    assert torch.equal(phis, torch.stack(want))
+    assert [B.decode_info(i.cpu().numpy()) for i in infos] == [B.decode_info(i[:24].cpu().numpy()) for i in winfo]
+    if prec == B.OCI_FP64:
+        ref = _oracle_time_dependent(p, qs, ls, rs, tol=1e-14)
+        assert rel(phis.cpu().numpy(), ref) <= 1e-9
+
+
+@pytest.mark.parametrize("name,solver", [("regions512_n64", B.OCI_SOLVE_DENSE), ("multigroup128_n256", B.OCI_SOLVE_DENSE),
+                                         ("multigroup128_n256", B.OCI_SOLVE_STRUCTURED)])
+def test_singular_cell_reported(name, solver, monkeypatch):
+    """A cell whose matrix has a zero pivot (the setup's test hook zeroes its
+    first column) makes oci_setup return OCI_ERR_SINGULAR and no handle,
+    through the C ABI, for both setup kernels and the structured setup."""
+    import ctypes as C
+    p, _ = CASES[name]
+    monkeypatch.setenv("OCI_TEST_ZERO_PIVOT_CELL", str(p["J"] // 2))
+    _announce(name, p, f"singular cell, solver={solver}")
+    d, keep = B.make_desc(p, solver=solver)
+    nbytes = B.oci_workspace_bytes(d)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+    h = C.c_void_p(1)
+    rc = B.lib().oci_setup(C.byref(d), ptr, nbytes, None, C.byref(h))
+    assert rc == B.OCI_ERR_SINGULAR
+    assert not h.value
+    monkeypatch.delenv("OCI_TEST_ZERO_PIVOT_CELL")
+    rc = B.lib().oci_setup(C.byref(d), ptr, nbytes, None, C.byref(h))
+    assert rc == B.OCI_OK and h.value
+    B.oci_destroy(h)
+
+
+# ------------------------------- red-black ordering, periodic mesh, history
+@pytest.mark.parametrize("name", ["homogeneous64_n32", "regions512_n64", "multigroup128_n256", "odd_N6_n24",
+                                  "G3_N16_n192", "N2_J5", "single_cell"])
+def test_structured_red_black_lockstep(name):
+    """Red-black OCI (even cells from the previous iterate, then odd cells
+    from the even cells' new values) against the oracle's red-black iteration
+    in lock-step (<= 1e-12)."""
+    p, steps = CASES[name]
+    K = 6
+    _announce(name, p, f"structured red-black lock-step K={K}")
+    want = oracle.Oracle(p).run("oci", steps=steps, fixed_iters=K, ordering=oracle.ORDER_RED_BLACK)
+    s = B.Solver(p, precision=B.OCI_FP64, fixed_iters=K, solver=B.OCI_SOLVE_STRUCTURED,
+                 ordering=B.OCI_ORDER_RED_BLACK)
+    got, infos = s.run(steps=steps, want_psi=True)
+    psi = s.psi.cpu().numpy()
+    s.close()
+    assert all(i["iterations"] == K and i["status"] == 0 for i in infos), infos
+    assert rel(got, want["phi"]) <= 1e-12
+    assert rel(psi, want["psi_iter"]) <= 1e-12
+
+
+def test_structured_red_black_converges_in_fewer_iterations():
+    """Converged red-black steps reach the Jacobi answer (the same fixed
+    point) in about half the iterations (the spectral radius squares)."""
+    p = dict(CASES["regions512_n64"][0], steps=2)
+    _announce("regions512_n64", p, "red-black vs Jacobi, converged")
+    out = {}
+    for ordering in (B.OCI_ORDER_JACOBI, B.OCI_ORDER_RED_BLACK):
+        s = B.Solver(p, precision=B.OCI_FP64, tol=1e-12, solver=B.OCI_SOLVE_STRUCTURED, ordering=ordering)
+        out[ordering] = s.run()
+        s.close()
+    ref = oracle.Oracle(p).run("oci", tol=1e-14)["phi"]
+    for ordering, (phi, infos) in out.items():
+        assert all(i["status"] == 0 for i in infos)
+        assert rel(phi, ref) <= 1e-10, ordering
+    ij = [i["iterations"] for i in out[B.OCI_ORDER_JACOBI][1]]
+    irb = [i["iterations"] for i in out[B.OCI_ORDER_RED_BLACK][1]]
+    print(f"  iterations per step: Jacobi {ij}, red-black {irb}", flush=True)
+    assert all(b < 0.7 * a for a, b in zip(ij, irb))
+
+
+@pytest.mark.parametrize("ordering", [B.OCI_ORDER_JACOBI, B.OCI_ORDER_RED_BLACK])
+def test_periodic_history_matches_oracle_and_fourier_symbol(ordering):
+    """The paper's verification setting (section 3.1) on a periodic mesh:
+    homogeneous slab, Sigma = 2.5, dx = 0.1, c = 0.9, dt = 0.1, v = 4 (tau = 1),
+    S8, no source and a random start.  The GPU's e_l history, filled by the
+    kernel in one run, equals the oracle's (periodic mesh), and its decay
+    rate, fitted while e_l stays far above its rounding floor, matches the
+    spectral radius of the Fourier symbol at the mesh's wave numbers (its
+    square for red-black)."""
+    J = 200
+    p = W.fourier_verification(J=J)
+    K, lo, hi = (60, 15, 55) if ordering == B.OCI_ORDER_JACOBI else (30, 6, 26)
+    _announce("fourier_verification_periodic", p, f"history, ordering {ordering}")
+    o = oracle.Oracle(p, periodic=True, methods=("oci",))
+    pp, pi = o.initial_state(p["psi_init"])
+    _, oinfo = o.step("oci", pp, pi, q=p["q"], fixed_iters=K, history=True, ordering=ordering)
+    want = oinfo["e_hist"]
+    s = B.Solver(p, precision=B.OCI_FP64, fixed_iters=K, solver=B.OCI_SOLVE_STRUCTURED, ordering=ordering,
+                 boundary=B.OCI_BOUNDARY_PERIODIC)
+    hist = torch.full((K + 8,), -1.0, dtype=torch.float64, device="cuda")
+    B.oci_set_history(s.h, hist, K)
+    _, infos = s.run(steps=1)
+    s.close()
+    got = hist.cpu().numpy()
+    assert infos[0]["iterations"] == K
+    assert np.all(got[K:] == -1.0)
+    floor = 1e-14 * np.sqrt(p["J"] * 4) * np.abs(want).max()
+    assert np.all(np.abs(got[:K] - want) <= 1e-11 * want + floor)
+    p1 = BAL.one_cell(p)
+    rho = max(np.abs(np.linalg.eigvals(BAL.oci_symbol(p1, 2 * np.pi * k / J))).max() for k in range(J))
+    if ordering == B.OCI_ORDER_RED_BLACK:
+        rho = rho ** 2
+    l = np.arange(lo, hi)
+    rate = np.exp(np.polyfit(l, np.log(got[lo:hi]), 1)[0])
+    print(f"  fitted rate {rate:.5f}, symbol radius {rho:.5f}, e_l from {got[lo]:.2e} to {got[hi - 1]:.2e}",
+          flush=True)
+    # the dominant eigenvalues are complex, so e_l oscillates about the decay
+    # (section 3.1): the fitted rate lands within a few percent of the radius
+    assert abs(rate - rho) < 0.05 * rho

@@ -42,6 +42,9 @@ MUTATIONS = {
                           "psi_prev[IDX2(p, j, g, m, 0)] = psi_iter[IDX4(p, j, g, m, 0)];\n                psi_prev[IDX2(p, j, g, m, 1)] = psi_iter[IDX4(p, j, g, m, 1)];\n            }\n    if (phi_out) memcpy(phi_out, phi_old, sizeof(double) * flen);\n    free(mu); free(w); free(next);"),
     "si_scatter_group": ("phi[((size_t)j * G + gp) * 4 + u];", "phi[((size_t)j * G + g) * 4 + u];"),
     "si_upstream_value": ("e0 = pos ? d[1] : d[0];", "e0 = pos ? d[0] : d[1];"),
+    "rb_black_from_old_iterate": ("const double *src = colour == 0 ? psi_in : psi_out;",
+                                  "const double *src = psi_in;"),
+    "rb_black_skipped": ("for (int j = colour; j < p->J; j += 2) {", "for (int j = 0; j < p->J; j += 2) {"),
     "flux_weight": ("for (int m = 0; m < p->N; ++m) s += w[m] * psi[IDX4(p, j, g, m, u)];",
                     "for (int m = 0; m < p->N; ++m) s += psi[IDX4(p, j, g, m, u)];"),
 }
@@ -90,6 +93,31 @@ def battery():
     ok = [l >= 1 and e[l] < 1e-8 * (1 - e[l] / e[l - 1]) for l in range(len(e))]
     if not (ok[-1] and not any(ok[:-1])):
         failed.append("stop_rule")
+    # red-black ordering: the same fixed point, and an iteration operator whose
+    # spectral radius is the square of the Jacobi one (2-cyclic coupling)
+    try:
+        o = oracle.Oracle(p)
+        pp, pi = o.initial_state(psi_prev)
+        _, info = o.step("oci", pp, pi, q=p["q"], inc_l=inc_l, inc_r=inc_r, tol=1e-14,
+                         max_iters=3000, ordering=oracle.ORDER_RED_BLACK)
+        if info["status"] != 0 or np.max(np.abs(pi - x)) > 1e-11 * scale:
+            failed.append("rb_fixed_point")
+    except RuntimeError:
+        failed.append("setup_rb")
+    pq = W.homogeneous(J=6, N=2, length=1.5, c=0.95, dt=0.4)
+    o = oracle.Oracle(pq, periodic=True, methods=("oci",))
+    nu = 6 * 2 * 4
+    radius = {}
+    for ordering in (oracle.ORDER_JACOBI, oracle.ORDER_RED_BLACK):
+        T = np.zeros((nu, nu))
+        for i in range(nu):
+            e1 = np.zeros(nu)
+            e1[i] = 1.0
+            T[:, i] = o.oci_iterate(e1.reshape(6, 1, 2, 4), np.zeros((6, 1, 2, 2)),
+                                    ordering=ordering).reshape(nu)
+        radius[ordering] = np.abs(np.linalg.eigvals(T)).max()
+    if abs(radius[oracle.ORDER_RED_BLACK] - radius[oracle.ORDER_JACOBI] ** 2) > 1e-10:
+        failed.append("rb_spectrum")
     # pivoting: a matrix with a zero leading entry
     A = np.array([[0.0, 1.0], [1.0, 1.0]])
     LU, piv, rc = oracle.lu_factor(A)

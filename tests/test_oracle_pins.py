@@ -532,3 +532,61 @@ def test_workload_recipes_match_table2():
     tau = p["sigma_t"][0, 1] * p["speed"][1] * np.array([10.0, 0.1])
     assert abs(tau[0] - g["mean_free_time_printed"]["dt_10s"]) < 1e-4
     assert abs(tau[1] - g["mean_free_time_printed"]["dt_0.1s"]) < 1e-4
+
+
+# --------------------------------------------------- red-black ordering
+def test_red_black_fixed_point_is_the_discrete_solution():
+    """The red-black OCI iteration reaches the same discrete solution (the
+    direct solve of the corner balances), in fewer iterations than Jacobi."""
+    p = tiny_mg()
+    inc_l, inc_r, psi_prev = nonzero_bc(p)
+    o = oracle.Oracle(p)
+    its = {}
+    for ordering in (oracle.ORDER_JACOBI, oracle.ORDER_RED_BLACK):
+        pp, pi = o.initial_state(psi_prev)
+        _, info = o.step("oci", pp, pi, q=p["q"], inc_l=inc_l, inc_r=inc_r, tol=1e-14,
+                         max_iters=20000, ordering=ordering)
+        assert info["status"] == 0
+        x = B.direct_solve(p, psi_prev, q=p["q"], inc_l=inc_l, inc_r=inc_r)
+        assert np.max(np.abs(pi - x)) / np.max(np.abs(x)) < 1e-12
+        its[ordering] = info["iterations"]
+    assert its[oracle.ORDER_RED_BLACK] < its[oracle.ORDER_JACOBI]
+
+
+def _oracle_operator(o, p, ordering):
+    J, N, G = p["J"], p["N"], p["G"]
+    nu = J * G * N * 4
+    zp = np.zeros((J, G, N, 2))
+    T = np.zeros((nu, nu))
+    for i in range(nu):
+        e = np.zeros(nu)
+        e[i] = 1.0
+        T[:, i] = o.oci_iterate(e.reshape(J, G, N, 4), zp, ordering=ordering).reshape(nu)
+    return T
+
+
+@pytest.mark.parametrize("periodic,J", [(True, 8), (False, 7)])
+@pytest.mark.parametrize("G", [1, 2])
+def test_red_black_spectrum_is_the_square_of_jacobi(periodic, J, G):
+    """Cells couple only to their two neighbours, so with red (even) and black
+    (odd) cells the block matrix is 2-cyclic and consistently ordered; the
+    red-black (block Gauss-Seidel) iteration operator then has as nonzero
+    eigenvalues exactly the squares of the block-Jacobi (OCI) operator's
+    (Young's theorem), and the spectral radius squares.  A periodic mesh
+    needs an even J for the colouring."""
+    N = 4
+    if G == 1:
+        p = W.homogeneous(J=J, N=N, length=0.25 * J, c=0.95, dt=0.4)
+    else:
+        p = W.multigroup(seed=9, J=J, N=N, G=G, n_regions=1, length=0.2 * J,
+                         speeds=(2.0, 1.0), dt=0.3)
+    o = oracle.Oracle(p, periodic=periodic, methods=("oci",))
+    ej = np.linalg.eigvals(_oracle_operator(o, p, oracle.ORDER_JACOBI))
+    erb = np.linalg.eigvals(_oracle_operator(o, p, oracle.ORDER_RED_BLACK))
+    rj, rrb = np.abs(ej).max(), np.abs(erb).max()
+    assert rj > 0.1
+    assert abs(rrb - rj ** 2) < 1e-10
+    # every nonzero red-black eigenvalue is the square of a Jacobi one
+    sq = ej ** 2
+    big = erb[np.abs(erb) > 1e-6]
+    assert max(np.min(np.abs(sq - v)) for v in big) < 1e-8
