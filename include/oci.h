@@ -89,8 +89,10 @@ typedef enum {
     OCI_ERR_UNSUPPORTED = -5,  /* shape or option beyond the compiled kernels (4NG > 512;
                                   the structured solve with FP32, the angular norm or
                                   G > 8; red-black or periodic without it) */
-    OCI_ERR_DEVICE = -6        /* a device-side wait expired (a workgroup of the
+    OCI_ERR_DEVICE = -6,       /* a device-side wait expired (a workgroup of the
                                   persistent launch was not co-resident) */
+    OCI_ERR_TOO_LARGE = -7     /* oci_setup_static: the workspace would exceed its
+                                  64 MiB static array */
 } oci_status;
 
 typedef enum { OCI_FP64 = 0, OCI_FP32_REFINED = 1 } oci_precision;
@@ -175,6 +177,21 @@ int oci_workspace_bytes(const oci_desc *desc, size_t *bytes);
  * caller until oci_destroy). */
 int oci_setup(const oci_desc *desc, void *workspace_dev, size_t workspace_bytes,
               void *stream, oci_handle **out);
+
+/* oci_setup without a caller-provided workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a 64 MiB array in the
+ * library's device memory, one per device, held from the library's load on
+ * that device until the process ends; this call allocates no device memory
+ * and calls no allocating routine.  A problem whose oci_workspace_bytes
+ * exceeds 64 MiB is rejected with OCI_ERR_TOO_LARGE before anything runs.
+ * Every handle this call returns on one device shares that device's array
+ * and the array keeps the last call's contents (the setup clears what a step
+ * needs to start from zero): a new oci_setup_static on the device takes the
+ * array over, so only the handle it returns may be used afterwards, and calls
+ * on two handles of one device that overlap in time race.  Otherwise the
+ * handle behaves as one from oci_setup (same kernels, same results). */
+int oci_setup_static(const oci_desc *desc, void *stream, oci_handle **out);
 
 /* Replace the state psi_{k-1/2}: psi_prev_dev [J][G][N][2] (L, R corners),
  * NULL = zero.  The first iterate of the next step becomes psi_prev copied to

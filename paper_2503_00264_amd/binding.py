@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "liboci.so")
 OCI_OK, OCI_NOT_CONVERGED, OCI_NONFINITE = 0, 1, 2
 OCI_ERR_INVALID, OCI_ERR_HIP, OCI_ERR_SINGULAR = -1, -2, -3
 OCI_ERR_WORKSPACE, OCI_ERR_UNSUPPORTED, OCI_ERR_DEVICE = -4, -5, -6
+OCI_ERR_TOO_LARGE = -7
 OCI_FP64, OCI_FP32_REFINED = 0, 1
 OCI_NORM_SCALAR, OCI_NORM_ANGULAR = 0, 1
 OCI_SOLVE_DENSE, OCI_SOLVE_STRUCTURED = 0, 1
@@ -27,7 +28,7 @@ OCI_ORDER_JACOBI, OCI_ORDER_RED_BLACK = 0, 1
 OCI_BOUNDARY_INCIDENT, OCI_BOUNDARY_PERIODIC = 0, 1
 
 # every symbol include/oci.h declares
-EXPORTS = ("oci_workspace_bytes", "oci_setup", "oci_set_state", "oci_get_state",
+EXPORTS = ("oci_workspace_bytes", "oci_setup", "oci_setup_static", "oci_set_state", "oci_get_state",
            "oci_step", "oci_run_steps", "oci_capture_steps", "oci_replay_steps", "si_step", "oci_profile_enable", "oci_profile_read",
            "oci_autotune", "oci_set_history", "oci_get_config", "oci_destroy", "oci_batch_workspace_bytes", "oci_batch_setup", "oci_batch_bind", "oci_batch_bind_steps",
            "oci_batch_step", "oci_batch_capture", "oci_batch_replay", "oci_batch_set_state",
@@ -70,6 +71,7 @@ def lib():
         D = C.POINTER(oci_desc)
         L.oci_workspace_bytes.argtypes = [D, C.POINTER(C.c_size_t)]
         L.oci_setup.argtypes = [D, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.oci_setup_static.argtypes = [D, vp, C.POINTER(vp)]
         L.oci_set_state.argtypes = [vp, vp]
         L.oci_get_state.argtypes = [vp, vp]
         L.oci_step.argtypes = [vp] * 7
@@ -152,6 +154,13 @@ def oci_setup(desc, workspace, nbytes, stream=None):
     h = C.c_void_p()
     _check("oci_setup", lib().oci_setup(C.byref(desc), _ptr(workspace), int(nbytes),
                                         _ptr(stream), C.byref(h)))
+    return h
+
+
+def oci_setup_static(desc, stream=None):
+    """oci_setup on the library's static device workspace (allocates nothing)."""
+    h = C.c_void_p()
+    _check("oci_setup_static", lib().oci_setup_static(C.byref(desc), _ptr(stream), C.byref(h)))
     return h
 
 

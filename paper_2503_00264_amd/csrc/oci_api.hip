@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -443,6 +444,41 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
     h->need_broadcast = true;
     *out = h;
     return OCI_OK;
+}
+
+// ------------------------------------------------------- static workspace
+// The device memory of oci_setup_static: one fixed array per device, created
+// when the library's code object is loaded on that device and held until the
+// process ends.  Host code never uses the array's name as an address: the
+// device address is looked up once per device (hipGetSymbolAddress, with that
+// device current) and kept in g_scratch.
+constexpr size_t kStaticWorkspaceBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+constexpr int kMaxDevices = 64;
+static void *g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static void *static_workspace(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch[dev] = p;
+    }
+    return g_scratch[dev];
+}
+
+extern "C" int oci_setup_static(const oci_desc *desc, void *stream, oci_handle **out) {
+    const int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!out) return OCI_ERR_INVALID;
+    *out = nullptr;
+    if (layout(desc, device_cus()).total > kStaticWorkspaceBytes) return OCI_ERR_TOO_LARGE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return OCI_ERR_HIP;
+    void *ws = static_workspace(dev);
+    if (!ws) return OCI_ERR_HIP;
+    return oci_setup(desc, ws, kStaticWorkspaceBytes, stream, out);
 }
 
 extern "C" int oci_set_state(oci_handle *h, const double *psi_prev_dev) {
@@ -1010,6 +1046,7 @@ extern "C" const char *oci_status_string(int s) {
     case OCI_ERR_SINGULAR: return "singular cell matrix (zero pivot)";
     case OCI_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
     case OCI_ERR_UNSUPPORTED: return "cell system larger than the compiled kernels (4 N G > 512)";
+    case OCI_ERR_TOO_LARGE: return "problem needs more than the 64 MiB static workspace of oci_setup_static";
     case OCI_ERR_DEVICE: return "device-side wait expired (a workgroup of the persistent launch was not co-resident)";
     default: return "unknown status";
     }
