@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--comparators", default="dense,sequential,red_black",
+                    help="batch64: which comparisons to run (dense, sequential, red_black)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--slabs", type=int, default=64, help="batch64: number of slabs")
     ap.add_argument("--no-comparison-workloads", action="store_true",
@@ -157,12 +159,23 @@ def summary(r, label, K, keys):
                 launch_shape=r["configs"][0], label=label, setup=r["setup"])
 
 
-def recorded_traffic(label, summary="pmc_traffic_regions4096.md", figure="HBM bytes per cell-iteration"):
+DENSE_SOURCES = ("oci_step.hip", "oci_device.hpp")
+STRUCTURED_SOURCES = ("oci_wb.hip", "oci_device.hpp")
+
+
+def source_digest(sources):
+    """sha256[:16] over the named kernel sources, in order."""
+    h = hashlib.sha256()
+    for f in sources:
+        h.update(open(os.path.join(ROOT, "paper_2503_00264_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(label, summary="pmc_traffic_regions4096.md", figure="HBM bytes per cell-iteration",
+                     sources=DENSE_SOURCES):
     """A traffic figure of `label` from a committed PMC summary (HBM bytes per
     cell-iteration, or per algorithmic byte), valid only while the kernel
-    source is the one the counters were taken on."""
-    src = os.path.join(ROOT, "paper_2503_00264_amd", "csrc", "oci_step.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sources are the ones the counters were taken on."""
     path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
@@ -170,7 +183,7 @@ def recorded_traffic(label, summary="pmc_traffic_regions4096.md", figure="HBM by
     m = re.search(r"source sha256\[:16\]: `([0-9a-f]+)`", text)
     k = re.search(r"kernel: `([^`]+)`", text)
     t = re.search(re.escape(figure) + r": ([0-9.]+)", text)
-    if not (m and k and t) or m.group(1) != digest or k.group(1) != label:
+    if not (m and k and t) or m.group(1) != source_digest(sources) or k.group(1) != label:
         return None
     return float(t.group(1))
 
@@ -447,11 +460,11 @@ def sequential(probs, K, tol, torch, B, method, precision):
 
 
 def batch_structured_bytes(probs):
-    """Algorithmic bytes per cell-iteration of the structured solve: the
-    constant part of b (4NG words), the incident and outgoing edges (2NG
-    words each), the scalar flux read and written (8G words) and the cell's
-    capacitance rows (2 x (2G)^2 complex words), all FP64."""
-    return np.array([8 * (4 * p["N"] * p["G"] + 4 * p["N"] * p["G"] + 8 * p["G"]) + 16 * 8 * p["G"] ** 2
+    """Algorithmic bytes per cell-iteration of the structured solve, FP64
+    words: psi_{k-1/2} (2NG), the incident and the outgoing corners (2NG
+    each), the source (4G), the scalar flux read and written (4G each) and the
+    cell's capacitance rows (2 x (2G)^2 complex words)."""
+    return np.array([8 * (6 * p["N"] * p["G"] + 12 * p["G"]) + 16 * 8 * p["G"] ** 2
                      for p in probs], dtype=np.float64)
 
 
@@ -486,10 +499,14 @@ def batch_main(a, torch, B):
     r = run_batch_graph(probs, K, a.warmup, a.tol, torch, B, B.OCI_FP64, B.OCI_SOLVE_STRUCTURED)
     head = batch_graph_summary(r, probs, K, batch_structured_bytes(probs), "k_wb_batch<256>")
     roof = head.pop("roofline")
-    roof["note"] = ("algorithmic bytes of the structured solve per cell-iteration (constant part of b, "
-                    "incident and outgoing corners, scalar flux, capacitance rows) times each slab's "
+    ratio = recorded_traffic("k_wb_batch<256>", "k_wb_batch_batch64.md", "HBM bytes per algorithmic byte",
+                             STRUCTURED_SOURCES)
+    roof["traffic"] = None if ratio is None else round(ratio * roof["bytes_per_step"], 1)
+    roof["note"] = ("algorithmic bytes of the structured solve per cell-iteration (psi_{k-1/2}, incident "
+                    "and outgoing corners, source, scalar flux, capacitance rows) times each slab's "
                     "cell-iterations, over the replayed graph's time per step (the per-step bookkeeping "
-                    "kernels included)")
+                    "kernels included); traffic = the committed counters' HBM bytes per algorithmic byte "
+                    "times this run's algorithmic bytes")
     out = {
         "metric": "cell-solves/s and s per converged step: FP32-refined vs FP64 OCI vs SI @1e-10",
         "value": round(head["cell_solves_per_s"], 1), "unit": "cell-solves/s", "n_gpus": 1, "steps": K,
@@ -509,8 +526,10 @@ def batch_main(a, torch, B):
         "s_per_converged_step": head["s_per_converged_step"],
         "batch": head,
     }
-    if not a.no_comparators:
+    which = set() if a.no_comparators else set(a.comparators.split(","))
+    if which:
         comp = out["comparison"] = {}
+    if "dense" in which:
         print("[bench] comparator: dense FP32-refined batched", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         rd = run_batch_graph(probs, K, a.warmup, a.tol, torch, B, B.OCI_FP32_REFINED)
@@ -522,6 +541,7 @@ def batch_main(a, torch, B):
                                         round(ratio * dense["roofline"]["bytes_per_step"], 1))
         dense["speedup_of_structured"] = round(rd["time_s"] / r["time_s"], 3)
         comp["dense_fp32_refined_batched"] = dense
+    if "sequential" in which:
         print("[bench] comparators: FP64 OCI and GPU SI, slab by slab", file=sys.stderr, flush=True)
         fp64 = sequential(probs, K, a.tol, torch, B, "oci", B.OCI_FP64)
         fp64["speedup_of_structured"] = round(fp64["time_s"] / r["time_s"], 3)
@@ -529,6 +549,7 @@ def batch_main(a, torch, B):
         si["speedup_of_structured"] = round(si["time_s"] / r["time_s"], 3)
         comp["dense_fp64_sequential"] = fp64
         comp["si_sequential"] = si
+    if "red_black" in which:
         print("[bench] comparator: structured red-black, batched", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         rr = run_batch_graph(probs, K, a.warmup, a.tol, torch, B, B.OCI_FP64, B.OCI_SOLVE_STRUCTURED,

@@ -201,6 +201,18 @@ int oci_set_state(oci_handle *h, const double *psi_prev_dev);
 /* Copy the state psi_{k-1/2} into psi_prev_dev [J][G][N][2]. Asynchronous. */
 int oci_get_state(const oci_handle *h, double *psi_prev_dev);
 
+/* Checkpoint for a bit-for-bit restart: everything a later step depends on
+ * besides the problem itself, psi_{k-1/2} [J][G][N][2] and the first iterate
+ * of the next step [J][G][N][4] (the last iterate of the previous step, or
+ * psi_prev on both time levels after oci_setup / oci_set_state; reading R3 of
+ * section 2.1's iteration).  oci_get_checkpoint copies both out;
+ * oci_set_checkpoint loads them into a handle set up from the same
+ * description, whose later steps then equal, bit for bit, those of the handle
+ * the checkpoint came from.  Asynchronous device-to-device copies on the
+ * handle's stream; all pointers device memory owned by the caller. */
+int oci_get_checkpoint(const oci_handle *h, double *psi_prev_dev, double *psi_iter_dev);
+int oci_set_checkpoint(oci_handle *h, const double *psi_prev_dev, const double *psi_iter_dev);
+
 /* One OCI time step (Algorithm 2; eq. oci).
  *   q_dev         [J][G][4] isotropic source Q at (k,L), (k,R), (k+1/2,L),
  *                 (k+1/2,R); NULL = no source

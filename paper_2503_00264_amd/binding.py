@@ -29,6 +29,7 @@ OCI_BOUNDARY_INCIDENT, OCI_BOUNDARY_PERIODIC = 0, 1
 
 # every symbol include/oci.h declares
 EXPORTS = ("oci_workspace_bytes", "oci_setup", "oci_setup_static", "oci_set_state", "oci_get_state",
+           "oci_get_checkpoint", "oci_set_checkpoint",
            "oci_step", "oci_run_steps", "oci_capture_steps", "oci_replay_steps", "si_step", "oci_profile_enable", "oci_profile_read",
            "oci_autotune", "oci_set_history", "oci_get_config", "oci_destroy", "oci_batch_workspace_bytes", "oci_batch_setup", "oci_batch_bind", "oci_batch_bind_steps",
            "oci_batch_step", "oci_batch_capture", "oci_batch_replay", "oci_batch_set_state",
@@ -74,6 +75,8 @@ def lib():
         L.oci_setup_static.argtypes = [D, vp, C.POINTER(vp)]
         L.oci_set_state.argtypes = [vp, vp]
         L.oci_get_state.argtypes = [vp, vp]
+        L.oci_get_checkpoint.argtypes = [vp, vp, vp]
+        L.oci_set_checkpoint.argtypes = [vp, vp, vp]
         L.oci_step.argtypes = [vp] * 7
         i64 = C.c_int64
         L.oci_run_steps.argtypes = [vp, i32, vp, i64, vp, vp, i64, vp, vp, vp]
@@ -170,6 +173,14 @@ def oci_set_state(h, psi_prev):
 
 def oci_get_state(h, psi_prev):
     _check("oci_get_state", lib().oci_get_state(h, _ptr(psi_prev)))
+
+
+def oci_get_checkpoint(h, psi_prev, psi_iter):
+    _check("oci_get_checkpoint", lib().oci_get_checkpoint(h, _ptr(psi_prev), _ptr(psi_iter)))
+
+
+def oci_set_checkpoint(h, psi_prev, psi_iter):
+    _check("oci_set_checkpoint", lib().oci_set_checkpoint(h, _ptr(psi_prev), _ptr(psi_iter)))
 
 
 def oci_step(h, q, inc_left, inc_right, phi_out, psi_out, info):
@@ -370,6 +381,21 @@ class Solver:
         out = self.torch.empty((self.J, self.G, self.N, 2), dtype=self.torch.float64, device=self.dev)
         oci_get_state(self.h, out)
         return out
+
+    def checkpoint(self):
+        """(psi_prev, first iterate of the next step) as device tensors."""
+        t = self.torch
+        pp = t.empty((self.J, self.G, self.N, 2), dtype=t.float64, device=self.dev)
+        pi = t.empty((self.J, self.G, self.N, 4), dtype=t.float64, device=self.dev)
+        oci_get_checkpoint(self.h, pp, pi)
+        self.stream.synchronize()
+        return pp, pi
+
+    def restore(self, psi_prev, psi_iter):
+        self._ckpt = (self._dev(psi_prev) if not hasattr(psi_prev, "data_ptr") else psi_prev,
+                      self._dev(psi_iter) if not hasattr(psi_iter, "data_ptr") else psi_iter)
+        self.torch.cuda.synchronize()
+        oci_set_checkpoint(self.h, *self._ckpt)
 
     def step(self, method="oci", want_psi=False):
         fn = oci_step if method == "oci" else si_step

@@ -37,9 +37,10 @@ hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp3
 hipError_t wb_batch_occupancy(int *blocks);
 hipError_t launch_flag_broadcast(const Slab &S, hipStream_t st);
 hipError_t launch_wb_setup(const Slab &S, hipStream_t st);
+hipError_t launch_checkpoint(const Slab &S, double *out, const double *in, bool from_state, hipStream_t st);
 hipError_t launch_oci_wb(const Slab &S, const StepIO &io, int nwg, int ntiles, hipStream_t st);
-hipError_t wb_occupancy(int NG, int *blocks);
-int wb_cells_per_tile(int NG);
+hipError_t wb_occupancy(int N, int G, int *blocks);
+int wb_cells_per_tile(int N, int G);
 int wb_block();
 }  // namespace oci
 
@@ -231,14 +232,13 @@ extern "C" int oci_workspace_bytes(const oci_desc *desc, size_t *bytes) {
 // inverse rows, then local with streamed rows, then the global-memory kernel
 // (resident, then streamed).  One tile = block / (threads per cell) cells.
 static int configure_structured(oci_handle *h, int gsz) {
-    const int NG = h->d.N * h->d.G;
-    const int cpt = wb_cells_per_tile(NG);
+    const int cpt = wb_cells_per_tile(h->d.N, h->d.G);
     const long cells = h->S.ordering == OCI_ORDER_RED_BLACK ? (h->d.J + 1) / 2 : h->d.J;   // per half-sweep
     const long ntiles = (cells + cpt - 1) / cpt;
     long cap = (long)h->num_cu * 8;   // partial-sum and barrier slots in the workspace
     if (h->max_wg > 0 && h->max_wg < cap) cap = h->max_wg;
     int occ = 0;
-    if (wb_occupancy(NG, &occ) != hipSuccess || occ < 1) return OCI_ERR_HIP;
+    if (wb_occupancy(h->d.N, h->d.G, &occ) != hipSuccess || occ < 1) return OCI_ERR_HIP;
     if ((long)occ * h->num_cu < cap) cap = (long)occ * h->num_cu;
     const long nwg = ntiles < cap ? ntiles : cap;
     h->block = wb_block();
@@ -496,6 +496,25 @@ extern "C" int oci_get_state(const oci_handle *h, double *psi_prev_dev) {
     const size_t bytes = (size_t)h->d.J * h->n / 2 * 8;
     if (hipMemcpyAsync(psi_prev_dev, h->S.psi_prev, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess)
         return OCI_ERR_HIP;
+    return OCI_OK;
+}
+
+extern "C" int oci_get_checkpoint(const oci_handle *h, double *psi_prev_dev, double *psi_iter_dev) {
+    if (!h || !psi_prev_dev || !psi_iter_dev) return OCI_ERR_INVALID;
+    const size_t bytes = (size_t)h->d.J * h->n / 2 * 8;
+    if (hipMemcpyAsync(psi_prev_dev, h->S.psi_prev, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess)
+        return OCI_ERR_HIP;
+    if (launch_checkpoint(h->S, psi_iter_dev, nullptr, h->need_broadcast, h->st) != hipSuccess) return OCI_ERR_HIP;
+    return OCI_OK;
+}
+
+extern "C" int oci_set_checkpoint(oci_handle *h, const double *psi_prev_dev, const double *psi_iter_dev) {
+    if (!h || !psi_prev_dev || !psi_iter_dev) return OCI_ERR_INVALID;
+    const size_t bytes = (size_t)h->d.J * h->n / 2 * 8;
+    if (hipMemcpyAsync(h->S.psi_prev, psi_prev_dev, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess)
+        return OCI_ERR_HIP;
+    if (launch_checkpoint(h->S, nullptr, psi_iter_dev, false, h->st) != hipSuccess) return OCI_ERR_HIP;
+    h->need_broadcast = false;
     return OCI_OK;
 }
 
@@ -819,7 +838,7 @@ static int batch_allocate(oci_batch *b, const std::vector<double> &weight) {
     for (int k = 0; k < nslab; ++k) {
         const oci_handle *h = b->slabs[k];
         const int rpt = h->np > bs ? h->np / bs : 1;
-        const int cpt = b->structured ? wb_cells_per_tile(h->d.N * h->d.G) : bs / (h->np / rpt);
+        const int cpt = b->structured ? wb_cells_per_tile(h->d.N, h->d.G) : bs / (h->np / rpt);
         const long cells = h->S.ordering == OCI_ORDER_RED_BLACK ? (h->d.J + 1) / 2 : h->d.J;
         ntile[k] = (cells + cpt - 1) / cpt;
         wsum += weight[k];

@@ -125,6 +125,29 @@ __global__ __launch_bounds__(kBlock) void k_broadcast_state(Slab S, int from_fla
 }
 __global__ void k_clear_bcast(Slab S) { S.ctl->bcast = 0; }
 
+// Checkpoints: the first iterate of the next step lives in buffer
+// (base + iter) & 1 of the control block (or is psi_prev on both levels when
+// the host still has to broadcast it).
+__global__ __launch_bounds__(kBlock) void k_checkpoint_get(Slab S, double *iter_out, int from_state) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (size_t)S.J * S.n) return;
+    const Ctl *c = S.ctl;
+    iter_out[t] = from_state ? S.psi_prev[(t >> 2) * 2 + (t & 1)] : S.psi[(c->base + c->iter) & 1][t];
+}
+__global__ __launch_bounds__(kBlock) void k_checkpoint_set(Slab S, const double *iter_in) {
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (size_t)S.J * S.n) return;
+    const Ctl *c = S.ctl;
+    S.psi[(c->base + c->iter) & 1][t] = iter_in[t];
+}
+hipError_t launch_checkpoint(const Slab &S, double *out, const double *in, bool from_state, hipStream_t st) {
+    const size_t tot = (size_t)S.J * S.n;
+    const dim3 grid((unsigned)((tot + kBlock - 1) / kBlock));
+    if (out) hipLaunchKernelGGL(k_checkpoint_get, grid, dim3(kBlock), 0, st, S, out, from_state ? 1 : 0);
+    else hipLaunchKernelGGL(k_checkpoint_set, grid, dim3(kBlock), 0, st, S, in);
+    return hipGetLastError();
+}
+
 // After a step: time update psi_{k-1/2} <- psi_{k+1/2} and the outputs.
 // Elements: one per (j, g, m) row quad and per phi entry.
 __device__ inline void end_elem(const Slab &S, const StepIO &io, size_t t) {

@@ -75,9 +75,26 @@ __device__ inline void corner_apply(cplx e2, cplx e3, cplx bk, cplx bh, cplx &xk
     xh = cadd(cadd(r, r), cmul(e3, bh));
 }
 
+// sum_c row[c] v[c] for c < R: the row's words are loaded four at a time
+// before their multiply-adds, so a row costs one memory round trip per four
+// words instead of one per word.
+__device__ inline cplx row_dot(const cplx *row, const cplx *v, int R) {
+    cplx acc{0.0, 0.0};
+    for (int c0 = 0; c0 < R; c0 += 4) {
+        cplx w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = c0 + k < R ? row[c0 + k] : cplx{0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c0 + k < R) acc = cadd(acc, cmul(w[k], v[c0 + k]));
+    }
+    return acc;
+}
+
 }  // namespace
 
-constexpr int kWbMaxG = 8;   // capacitance systems up to 2G = 16 complex unknowns
+constexpr int kWbMaxG = 8;     // capacitance systems up to 2G = 16 complex unknowns
+constexpr int kWbMaxN = 128;   // quadrature nodes staged in LDS
 
 // ------------------------------------------------------------------ setup
 // One wave per cell: W_g (moments of the corner inverses, ascending m), the
@@ -215,7 +232,7 @@ struct WbLds {
 template <int Q, int BS>
 __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, const StepIO &io, int ntiles, int wg,
                                                          unsigned nwg, cplx *lds, double *s_tmp, int *s_flag,
-                                                         double *s_ivdt) {
+                                                         double *s_ivdt, double *s_mu, double *s_w) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int J = S.J, N = S.N, G = S.G, NG = N * G, nh = N / 2, R = 2 * G;
     const WbShape sh = wb_shape(NG);
@@ -230,6 +247,7 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
     const int tile0 = (int)(((long)ntiles * wg) / nwg);
     const int tile1 = (int)(((long)ntiles * (wg + 1)) / nwg);
     for (int g = tid; g < G; g += BS) s_ivdt[g] = 1.0 / (S.speed[g] * S.dt);
+    for (int m = tid; m < N; m += BS) { s_mu[m] = S.mu[m]; s_w[m] = S.w[m]; }
     __syncthreads();
     // outgoing corners of iteration l go to the compact edge buffer of parity
     // l, through coherent stores (other workgroups read them after the grid
@@ -254,7 +272,7 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
         double *__restrict__ phi_out = S.phi[cur ^ 1];
         double *__restrict__ e_out = S.edge + (size_t)(l & 1) * ehalf;
         const double *__restrict__ e_in = S.edge + (size_t)((l + 1) & 1) * ehalf;
-        double wg_sum = 0.0;
+        double dsq = 0.0;   // summed per lane over its tiles in order, reduced once per iteration
         bool fin = false;
         // one pass per iteration; after a stop, one more pass over the same
         // inputs writes the whole final iterate
@@ -271,6 +289,12 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
                 const int j = rb ? 2 * cc + half : cc;
                 const bool cell = j < J;
                 const double dx = cell ? S.dx[j] : 0.0;
+                // this lane's entry of the previous scalar flux (a cell's first
+                // R lanes, one (g, level) each: R = 2G <= NG <= lanes per cell),
+                // loaded early so that its latency hides behind the solves
+                double2 fprev{0.0, 0.0};
+                if (cell && pass == 0 && li < R)
+                    fprev = *reinterpret_cast<const double2 *>(phi_in + (size_t)j * 4 * G + 2 * li);
                 cplx z[Q][2], e2[Q], e3[Q];
                 // (1) b = constant part + lagged incident edge (eq. rhs_sg);
                 //     z = L_c^-1 b; the weighted z into LDS for the moments
@@ -282,7 +306,7 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
                     cplx wz0{0.0, 0.0}, wz1{0.0, 0.0};
                     if (cell && i < NG) {
                         const int g = i / N, m = i % N;
-                        const double mu = S.mu[m];
+                        const double mu = s_mu[m];
                         const size_t row = ((size_t)j * G + g) * N + m;
                         // constant part of b (eq. rhs_sg): dx/4 Q, plus dx/(2 v dt)
                         // psi_{k-1/2} in the level-k rows
@@ -334,7 +358,7 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
                         }
                         corner_inverse(mu, dx * S.sigma_t[(size_t)j * G + g], dx * s_ivdt[g], e2[q], e3[q]);
                         corner_apply(e2[q], e3[q], cplx{b0, -b1}, cplx{b2, -b3}, z[q][0], z[q][1]);
-                        const double w = S.w[m];
+                        const double w = s_w[m];
                         wz0 = cscale(w, z[q][0]);
                         wz1 = cscale(w, z[q][1]);
                     }
@@ -357,14 +381,8 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
                 cplx r0{0.0, 0.0}, r1{0.0, 0.0};
                 if (cell) {
                     const cplx *Mj = reinterpret_cast<const cplx *>(S.wb) + (size_t)j * 2 * R * R;
-                    if (o0 < 2 * R) {
-                        const cplx *row = Mj + (size_t)o0 * R;
-                        for (int c = 0; c < R; ++c) r0 = cadd(r0, cmul(row[c], Zcell[c]));
-                    }
-                    if (o1 < 2 * R) {
-                        const cplx *row = Mj + (size_t)o1 * R;
-                        for (int c = 0; c < R; ++c) r1 = cadd(r1, cmul(row[c], Zcell[c]));
-                    }
+                    if (o0 < 2 * R) r0 = row_dot(Mj + (size_t)o0 * R, Zcell, R);
+                    if (o1 < 2 * R) r1 = row_dot(Mj + (size_t)o1 * R, Zcell, R);
                 }
                 wave_sync();   // area A's weighted z is no longer needed
                 if (cell && o0 < 2 * R) Tcell[o0] = r0;
@@ -395,22 +413,13 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
                     }
                 }
                 // (5) the scalar flux is t itself; its change for the norm
-                double dsq = 0.0;
-                if (cell && pass == 0)
-                    for (int o = li; o < R; o += sh.lc) {
-                        const cplx t = Tcell[o];
-                        const size_t f = (size_t)j * 4 * G + 2 * o;
-                        const double f0 = phi_in[f], f1 = phi_in[f + 1];
-                        const double n0 = t.re, n1 = -t.im;
-                        phi_out[f] = n0;
-                        phi_out[f + 1] = n1;
-                        dsq += (n0 - f0) * (n0 - f0) + (n1 - f1) * (n1 - f1);
-                    }
-                wave_sync();   // area A is rewritten by the next tile
-                if (pass == 0) {
-                    const double part = block_sum_t<BS>(dsq, s_tmp);
-                    if (tid == 0) wg_sum += part;
+                if (cell && pass == 0 && li < R) {
+                    const cplx t = Tcell[li];
+                    const double n0 = t.re, n1 = -t.im;
+                    *reinterpret_cast<double2 *>(phi_out + (size_t)j * 4 * G + 2 * li) = double2{n0, n1};
+                    dsq += (n0 - fprev.x) * (n0 - fprev.x) + (n1 - fprev.y) * (n1 - fprev.y);
                 }
+                wave_sync();   // area A is rewritten by the next tile
             }
             // red-black: the odd cells wait for every even cell's new edges
             // (a grid barrier whose sum is not used)
@@ -421,6 +430,7 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
             }
             if (pass == 1) break;
             // (6) grid barrier + reduction; every workgroup decides identically
+            const double wg_sum = block_sum_t<BS>(dsq, s_tmp);   // valid in thread 0
             double tot = 0.0;
             if (!grid_sync_coherent<BS>(S, wg, nwg, rb ? 2 * l + 1 : l, wg_sum, s_flag, s_tmp, &tot)) return;
             const int iters = l + 1;
@@ -456,7 +466,8 @@ __global__ __launch_bounds__(BS) void k_oci_wb(Slab S, StepIO io, int ntiles) {
     __shared__ double s_tmp[BS / 64 + 1];
     __shared__ int s_flag[4];
     __shared__ double s_ivdt[kWbMaxG];
-    wb_body<Q, BS>(S, io, ntiles, blockIdx.x, gridDim.x, s_lds, s_tmp, s_flag, s_ivdt);
+    __shared__ double s_mu[kWbMaxN], s_w[kWbMaxN];
+    wb_body<Q, BS>(S, io, ntiles, blockIdx.x, gridDim.x, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
 }
 
 // Many slabs in one persistent launch: slab k owns the workgroups
@@ -469,6 +480,7 @@ __global__ __launch_bounds__(BS) void k_wb_batch(const BatchEntry *tab, int nsla
     __shared__ double s_tmp[BS / 64 + 1];
     __shared__ int s_flag[4];
     __shared__ double s_ivdt[kWbMaxG];
+    __shared__ double s_mu[kWbMaxN], s_w[kWbMaxN];
     __shared__ int s_k;
     if (threadIdx.x == 0) {
         int lo = 0, hi = nslab - 1;     // last entry with wg0 <= blockIdx.x
@@ -483,9 +495,9 @@ __global__ __launch_bounds__(BS) void k_wb_batch(const BatchEntry *tab, int nsla
     const int lw = (int)blockIdx.x - e.wg0;
     if (lw < 0 || lw >= e.nwg) return;
     if (e.S.N * e.S.G > 64)
-        wb_body<2, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt);
+        wb_body<2, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
     else
-        wb_body<1, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt);
+        wb_body<1, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
 }
 
 constexpr int kWbBlock = 256;
@@ -499,12 +511,11 @@ hipError_t launch_wb_batch(const BatchEntry *tab, int nslab, int nwg, hipStream_
     return hipGetLastError();
 }
 
-int wb_quads_per_lane(int NG) { return NG > 64 ? 2 : 1; }
-int wb_cells_per_tile(int NG) { return (kWbBlock / 64) * wb_shape(NG).cpw; }
+int wb_cells_per_tile(int N, int G) { return (kWbBlock / 64) * wb_shape(N * G).cpw; }
 int wb_block() { return kWbBlock; }
 
-hipError_t wb_occupancy(int NG, int *blocks) {
-    const void *f = NG > 64 ? (const void *)&k_oci_wb<2, kWbBlock> : (const void *)&k_oci_wb<1, kWbBlock>;
+hipError_t wb_occupancy(int N, int G, int *blocks) {
+    const void *f = N * G > 64 ? (const void *)&k_oci_wb<2, kWbBlock> : (const void *)&k_oci_wb<1, kWbBlock>;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, kWbBlock, 0);
 }
 

@@ -736,3 +736,32 @@ def test_periodic_history_matches_oracle_and_fourier_symbol(ordering):
     # the dominant eigenvalues are complex, so e_l oscillates about the decay
     # (section 3.1): the fitted rate lands within a few percent of the radius
     assert abs(rate - rho) < 0.05 * rho
+
+
+@pytest.mark.parametrize("prec,solver", [(B.OCI_FP64, B.OCI_SOLVE_DENSE), (B.OCI_FP32_REFINED, B.OCI_SOLVE_DENSE),
+                                         (B.OCI_FP64, B.OCI_SOLVE_STRUCTURED)])
+def test_checkpoint_restart_is_bitwise(prec, solver):
+    """Ten steps in one run equal five steps, a checkpoint (psi_{k-1/2} and
+    the next first iterate), a fresh handle restored from it and five more
+    steps, bit for bit: fluxes, step reports and the final state."""
+    p = dict(W.multigroup(seed=9, J=96, N=8, G=2, n_regions=8, length=2.0, speeds=(3.0, 1.0), dt=0.2,
+                          steps=10))
+    _announce("checkpoint", p, f"10 steps vs 5 + checkpoint + 5, prec={prec}, solver={solver}")
+    kw = dict(precision=prec, tol=1e-10, solver=solver)
+    a = B.Solver(p, **kw)
+    want, winfo = a.run(steps=10)
+    wstate = a.get_state().cpu().numpy()
+    a.close()
+    b = B.Solver(p, **kw)
+    first, _ = b.run(steps=5)
+    pp, pi = b.checkpoint()
+    b.close()
+    c = B.Solver(p, **kw)
+    c.restore(pp, pi)
+    rest, rinfo = c.run(steps=5)
+    rstate = c.get_state().cpu().numpy()
+    c.close()
+    assert np.array_equal(first, want[:5])
+    assert np.array_equal(rest, want[5:])
+    assert rinfo == winfo[5:]
+    assert np.array_equal(rstate, wstate)
