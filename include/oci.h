@@ -308,7 +308,8 @@ int oci_autotune(oci_handle *h, int32_t iters, int32_t *config);
  * multi-step launch leaves the last step's record).  NULL turns it off. */
 int oci_set_history(oci_handle *h, double *e_hist_dev, int32_t capacity);
 
-/* Current launch shape: config[6] = {threads per workgroup, local kernel (0/1),
+/* Current launch shape: config[6] = {threads per workgroup, local kernel (0/1;
+ * for the structured solve: tile inputs staged in LDS ahead of the arithmetic),
  * register-resident rows (0/1), barrier group size, workgroups, tiles}. */
 int oci_get_config(const oci_handle *h, int32_t *config);
 

@@ -32,14 +32,15 @@ hipError_t launch_si_iteration(const Slab &S, const StepIO &io, hipStream_t st);
 size_t si_flux_blocks(const Slab &S);
 hipError_t batch_occupancy(bool fp32, int *blocks);
 int batch_block();
-hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp32, bool structured, bool broadcast,
-                             hipStream_t st, bool coop);
-hipError_t wb_batch_occupancy(int *blocks);
+hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp32, bool structured, bool staged,
+                             bool broadcast, hipStream_t st, bool coop);
+hipError_t wb_batch_occupancy(bool staged, int *blocks);
 hipError_t launch_flag_broadcast(const Slab &S, hipStream_t st);
 hipError_t launch_wb_setup(const Slab &S, hipStream_t st);
 hipError_t launch_checkpoint(const Slab &S, double *out, const double *in, bool from_state, hipStream_t st);
-hipError_t launch_oci_wb(const Slab &S, const StepIO &io, int nwg, int ntiles, hipStream_t st);
-hipError_t wb_occupancy(int N, int G, int *blocks);
+hipError_t launch_oci_wb(const Slab &S, const StepIO &io, int nwg, int ntiles, bool staged, hipStream_t st);
+hipError_t wb_occupancy(int N, int G, bool staged, int *blocks);
+bool wb_staged(long J, int N, int G);
 int wb_cells_per_tile(int N, int G);
 int wb_block();
 }  // namespace oci
@@ -61,6 +62,7 @@ struct oci_handle {
     bool resident;
     bool local;            // workgroup-local kernel (iterate kept in LDS)
     bool structured;       // structured cell solve (OCI_SOLVE_STRUCTURED)
+    bool wb_staged;        // ... with the staged iteration body (shape permitting)
     size_t dyn_lds;        // its dynamic LDS bytes
     bool need_broadcast;   // next step starts from psi_prev on both levels
     int32_t h_flag;        // host copy of the done flag for SI's convergence polling
@@ -238,7 +240,7 @@ static int configure_structured(oci_handle *h, int gsz) {
     long cap = (long)h->num_cu * 8;   // partial-sum and barrier slots in the workspace
     if (h->max_wg > 0 && h->max_wg < cap) cap = h->max_wg;
     int occ = 0;
-    if (wb_occupancy(h->d.N, h->d.G, &occ) != hipSuccess || occ < 1) return OCI_ERR_HIP;
+    if (wb_occupancy(h->d.N, h->d.G, h->wb_staged, &occ) != hipSuccess || occ < 1) return OCI_ERR_HIP;
     if ((long)occ * h->num_cu < cap) cap = (long)occ * h->num_cu;
     const long nwg = ntiles < cap ? ntiles : cap;
     h->block = wb_block();
@@ -376,6 +378,10 @@ extern "C" int oci_setup(const oci_desc *desc, void *workspace_dev, size_t works
     S.wb = desc->solver == OCI_SOLVE_STRUCTURED ? (double *)(ws + L.wb) : nullptr;
     S.edge = desc->solver == OCI_SOLVE_STRUCTURED ? (double *)(ws + L.edge) : nullptr;
     h->structured = S.wb != nullptr;
+    // the staged structured body where the shape allows it; OCI_WB_DIRECT=1
+    // selects the direct body (testing both on one shape)
+    const char *direct = getenv("OCI_WB_DIRECT");
+    h->wb_staged = h->structured && wb_staged(desc->J, desc->N, desc->G) && !(direct && atoi(direct) == 1);
     S.ctl = (Ctl *)(ws + L.ctl);
     S.bar = (uint64_t *)(ws + L.bar);
     S.bar_groups = L.bar_groups;
@@ -534,7 +540,7 @@ extern "C" int oci_step(oci_handle *h, const double *q_dev, const double *inc_le
     hipEvent_t e0 = h->profiling ? prof_event(h) : nullptr, e1 = h->profiling ? prof_event(h) : nullptr;
     if (e0) HIPCHECK(hipEventRecord(e0, h->st));
     if (h->structured)
-        HIPCHECK(launch_oci_wb(h->S, io, h->nwg, h->ntiles, h->st));
+        HIPCHECK(launch_oci_wb(h->S, io, h->nwg, h->ntiles, h->wb_staged, h->st));
     else if (h->local)
         HIPCHECK(launch_oci_local(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->dyn_lds, h->st));
     else
@@ -588,7 +594,7 @@ extern "C" int oci_run_steps(oci_handle *h, int32_t nsteps, const double *q_dev,
 static hipError_t enqueue_step_for_graph(oci_handle *h, const StepIO &io) {
     hipError_t e = launch_begin(h->S, io, 2, h->st, h->local ? h->nwg : 0);
     if (e != hipSuccess) return e;
-    if (h->structured) e = launch_oci_wb(h->S, io, h->nwg, h->ntiles, h->st);
+    if (h->structured) e = launch_oci_wb(h->S, io, h->nwg, h->ntiles, h->wb_staged, h->st);
     else if (h->local)
         e = launch_oci_local(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->dyn_lds, h->st);
     else e = launch_oci_step(h->S, io, h->fp32, h->np, h->resident, h->block, h->nwg, h->ntiles, h->st, false);
@@ -757,7 +763,7 @@ extern "C" int oci_set_history(oci_handle *h, double *e_hist_dev, int32_t capaci
 extern "C" int oci_get_config(const oci_handle *h, int32_t *config) {
     if (!h || !config) return OCI_ERR_INVALID;
     config[0] = h->block;
-    config[1] = h->local ? 1 : 0;
+    config[1] = (h->structured ? h->wb_staged : h->local) ? 1 : 0;
     config[2] = h->resident ? 1 : 0;
     config[3] = h->S.bar_gsz;
     config[4] = h->nwg;
@@ -781,6 +787,7 @@ struct oci_batch {
     int nslab;
     bool fp32;
     bool structured;
+    bool wb_staged;   // every slab takes the staged structured body
     hipStream_t st;
     std::vector<oci_handle *> slabs;
     std::vector<BatchEntry> tab;   // host copy of the device tables, [nbound][nslab]
@@ -915,7 +922,9 @@ extern "C" int oci_batch_setup(int32_t nslab, const oci_desc *descs, void *works
         off += align256(bk);
     }
     int occ = 0;
-    const hipError_t oe = b->structured ? wb_batch_occupancy(&occ) : batch_occupancy(b->fp32, &occ);
+    b->wb_staged = b->structured;
+    for (int k = 0; k < nslab; ++k) b->wb_staged = b->wb_staged && b->slabs[k]->wb_staged;
+    const hipError_t oe = b->structured ? wb_batch_occupancy(b->wb_staged, &occ) : batch_occupancy(b->fp32, &occ);
     if (oe != hipSuccess || occ < 1) { oci_batch_destroy(b); return OCI_ERR_HIP; }
     b->occ = occ;
     b->tab.resize(nslab);
@@ -978,7 +987,7 @@ extern "C" int oci_batch_bind(oci_batch *b, const double *const *q_dev, const do
 
 extern "C" int oci_batch_step(oci_batch *b) {
     if (!b || b->nbound < 1) return OCI_ERR_INVALID;
-    HIPCHECK(launch_batch_step(batch_dtab(b, b->cursor), b->nslab, b->nwg, b->fp32, b->structured, false, b->st, true));
+    HIPCHECK(launch_batch_step(batch_dtab(b, b->cursor), b->nslab, b->nwg, b->fp32, b->structured, b->wb_staged, false, b->st, true));
     b->last = b->cursor;
     b->cursor = (b->cursor + 1) % b->nbound;
     return OCI_OK;
@@ -990,7 +999,7 @@ extern "C" int oci_batch_capture(oci_batch *b, int32_t n_steps) {
     HIPCHECK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int k = 0; k < n_steps && e == hipSuccess; ++k)
-        e = launch_batch_step(batch_dtab(b, (b->cursor + k) % b->nbound), b->nslab, b->nwg, b->fp32, b->structured,
+        e = launch_batch_step(batch_dtab(b, (b->cursor + k) % b->nbound), b->nslab, b->nwg, b->fp32, b->structured, b->wb_staged,
                               false, b->st, false);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->st, &g);

@@ -1742,16 +1742,16 @@ hipError_t launch_flag_broadcast(const Slab &S, hipStream_t st) {
 // One batched time step: bookkeeping for all slabs, the persistent launch,
 // the end-of-step kernel.  No memset and no host synchronisation, so the
 // sequence can be captured into a graph (then with a normal launch).
-hipError_t launch_wb_batch(const BatchEntry *tab, int nslab, int nwg, hipStream_t st);
+hipError_t launch_wb_batch(const BatchEntry *tab, int nslab, int nwg, bool staged, hipStream_t st);
 
-hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp32, bool structured, bool broadcast,
-                             hipStream_t st, bool coop) {
+hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp32, bool structured, bool staged,
+                             bool broadcast, hipStream_t st, bool coop) {
     hipLaunchKernelGGL(k_batch_begin, dim3(nslab), dim3(1), 0, st, tab);
     hipLaunchKernelGGL(k_batch_elems, dim3(256, nslab), dim3(kBlock), 0, st, tab, 0, broadcast ? 1 : 0);
     hipLaunchKernelGGL(k_batch_elems, dim3(64, nslab), dim3(kBlock), 0, st, tab, 1, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = structured ? launch_wb_batch(tab, nslab, nwg, st)
+    e = structured ? launch_wb_batch(tab, nslab, nwg, staged, st)
         : fp32     ? batch_launch_t<float, kBatchBlock>(tab, nslab, nwg, st, coop)
                    : batch_launch_t<double, kBatchBlock>(tab, nslab, nwg, st, coop);
     if (e != hipSuccess) return e;

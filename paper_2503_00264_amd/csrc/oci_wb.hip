@@ -223,6 +223,32 @@ __host__ __device__ inline WbShape wb_shape(int NG) {
 // LDS per wave, in complex words: area A holds the weighted corner solutions
 // w_m z of the wave's pairs, then the rows' results t and C t (4G per cell);
 // area B the moments V^T z (2G per cell).
+// The stopping rule after iteration l (0-based) from the squared norm of the
+// scalar-flux change; every workgroup takes the same decision.  Returns true
+// when the step ends (thread 0 of workgroup 0 records the outcome).
+__device__ inline bool wb_decide(const Slab &S, int wg, int l, double tot, double &e_prev) {
+    const int iters = l + 1;
+    const double e = sqrt(tot);
+    const double rho = iters >= 2 ? e / e_prev : __builtin_nan("");
+    int done = 0, status = OK;
+    if (!isfinite(e)) { done = 1; status = NONFINITE; }
+    else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
+    else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - e / e_prev))) done = 1;
+    else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
+    e_prev = e;
+    if (S.hist && iters <= S.hist_cap && wg == 0 && threadIdx.x == 0) S.hist[iters - 1] = e;
+    if (done && wg == 0 && threadIdx.x == 0) {
+        Ctl *c = S.ctl;
+        c->iter = iters;
+        c->e_last = e;
+        c->rho = rho;
+        c->e_prev = e;
+        c->status = status;
+        c->done = 1;
+    }
+    return done != 0;
+}
+
 template <int Q>
 struct WbLds {
     static constexpr int kA = 128 * Q;
@@ -433,50 +459,447 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
             const double wg_sum = block_sum_t<BS>(dsq, s_tmp);   // valid in thread 0
             double tot = 0.0;
             if (!grid_sync_coherent<BS>(S, wg, nwg, rb ? 2 * l + 1 : l, wg_sum, s_flag, s_tmp, &tot)) return;
-            const int iters = l + 1;
-            const double e = sqrt(tot);
-            const double rho = iters >= 2 ? e / e_prev : __builtin_nan("");
-            int done = 0, status = OK;
-            if (!isfinite(e)) { done = 1; status = NONFINITE; }
-            else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
-            else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - e / e_prev))) done = 1;
-            else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
-            e_prev = e;
-            if (S.hist && iters <= S.hist_cap && wg == 0 && tid == 0) S.hist[iters - 1] = e;
-            if (done) {
-                if (wg == 0 && tid == 0) {
-                    Ctl *c = S.ctl;
-                    c->iter = iters;
-                    c->e_last = e;
-                    c->rho = rho;
-                    c->e_prev = e;
-                    c->status = status;
-                    c->done = 1;
-                }
-                fin = true;
-            }
+            fin = wb_decide(S, wg, l, tot, e_prev);
         }
         if (fin) return;
     }
 }
 
+// ------------------------------------------------------ staged iteration
+// The same iteration with the inputs of a tile staged into LDS by the memory
+// system (global_load_lds: the data lands in LDS without passing through
+// registers), one tile ahead of the arithmetic, so a wave keeps a tile's worth
+// of loads in flight while it computes the previous tile.  Per tile t a wave
+//   waits for its staged inputs of t (psi_{k-1/2}, upstream corners, the
+//   cells' sources, scalar flux, cross sections and widths);
+//   forms b and z = L_c^-1 b; sums the moments over m by a butterfly across
+//   the N lanes of each group; then issues the staging of t + 1;
+//   waits for the rows of (I - W C)^-1 of t (issued one tile earlier), forms
+//   t = (I - W C)^-1 V^T z and C t = (dx/4) (Sigma_s (x) I) t; stores the new
+//   scalar flux; then issues the rows of t + 1;
+//   forms x = z + L_c^-1 (C t)_g and stores the outgoing corners.
+// Vector memory operations complete in issue order, so "the loads of t have
+// landed" is "at most k operations are outstanding", k the number issued
+// after them; every staging load and every store is issued by all 64 lanes
+// (addresses of idle lanes clamped into the slab, stores of idle lanes sent
+// past the end of a buffer resource, which drops them), so k is known.
+// Shapes: N a power of two in [8, 64], G in {1, 2, 4}, at most two pairs per
+// lane, a wave's rows of (I - W C)^-1 within 2 KiB and its per-cell data
+// within 1 KiB (wb_staged_shape); other shapes take the direct body above.
+typedef __attribute__((address_space(3))) void lds_void;
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline bool wb_staged_shape(long J, int N, int G) {
+    if (N < 8 || N > 64 || (N & (N - 1))) return false;
+    if (G != 1 && G != 2 && G != 4) return false;
+    const int NG = N * G;
+    if (NG > 128) return false;
+    const WbShape sh = wb_shape(NG);
+    if (sh.cpw * 4 * G * G > 128) return false;                          // rows: 128 complex words
+    if (sh.cpw * (16 * G + 2 * G * G + 2 * G + 2) > 256) return false;   // per-cell data: 256 dwords
+    return J * NG * 32 < (1L << 31);                                     // 32-bit buffer offsets
+}
+
+// Byte layout of one wave's LDS area in the staged body.
+template <int Q>
+struct WbStage {
+    static constexpr int kP = 0;               // psi_{k-1/2} of the lanes' pairs: [Q][64] x 16 B
+    static constexpr int kE = kP + Q * 1024;   // upstream corners: [Q][64] x 16 B, or [Q][4][64] dwords
+    static constexpr int kC = kE + Q * 1024;   // per-cell data: 256 dwords
+    static constexpr int kM = kC + 1024;       // rows of (I - W C)^-1: 128 complex words
+    static constexpr int kB = kM + 2048;       // moments V^T z: 16 complex words
+    static constexpr int kT = kB + 256;        // t, then C t: 32 complex words
+    static constexpr int kBytes = kT + 512;
+};
+
+// s_waitcnt vmcnt(k) for a wave-uniform k; k above 31 waits for 31 (more
+// than asked, never less).
+#define OCI_VMW(n) \
+    case n: asm volatile("s_waitcnt vmcnt(" #n ")" ::: "memory"); break;
+__device__ inline void vm_wait(int k) {
+    switch (k < 0 ? 0 : (k > 31 ? 31 : k)) {
+        OCI_VMW(0) OCI_VMW(1) OCI_VMW(2) OCI_VMW(3) OCI_VMW(4) OCI_VMW(5) OCI_VMW(6) OCI_VMW(7)
+        OCI_VMW(8) OCI_VMW(9) OCI_VMW(10) OCI_VMW(11) OCI_VMW(12) OCI_VMW(13) OCI_VMW(14) OCI_VMW(15)
+        OCI_VMW(16) OCI_VMW(17) OCI_VMW(18) OCI_VMW(19) OCI_VMW(20) OCI_VMW(21) OCI_VMW(22) OCI_VMW(23)
+        OCI_VMW(24) OCI_VMW(25) OCI_VMW(26) OCI_VMW(27) OCI_VMW(28) OCI_VMW(29) OCI_VMW(30) OCI_VMW(31)
+        default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+}
+#undef OCI_VMW
+
+// The wave's LDS reads issued so far have returned (before the memory system
+// may overwrite what they read); also a compiler barrier for memory accesses.
+__device__ inline void lds_reads_done() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// 16 bytes (lane i's at lds + 16 i) or 4 bytes (at lds + 4 i) from each
+// lane's address into LDS; SC1: agent-coherent, as ld_coherent.  Written as
+// inline assembly so that the compiler, which cannot tell the staging areas
+// apart, does not wait for every staging load before each LDS read: the body
+// orders them itself (vm_wait).  M0 (the LDS base) is saved and restored.
+template <bool SC1>
+__device__ inline void stage16(const void *src, unsigned char *lds) {
+    const unsigned base = __builtin_amdgcn_readfirstlane((unsigned)(size_t)(lds_void *)lds);
+    unsigned saved;
+    if (SC1)
+        asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off sc1\n\t"
+                     "s_mov_b32 m0, %0"
+                     : "=&s"(saved) : "v"(src), "s"(base) : "memory");
+    else
+        asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off\n\t"
+                     "s_mov_b32 m0, %0"
+                     : "=&s"(saved) : "v"(src), "s"(base) : "memory");
+}
+__device__ inline void stage4(const void *src, unsigned char *lds) {
+    const unsigned base = __builtin_amdgcn_readfirstlane((unsigned)(size_t)(lds_void *)lds);
+    unsigned saved;
+    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %1, off\n\t"
+                 "s_mov_b32 m0, %0"
+                 : "=&s"(saved) : "v"(src), "s"(base) : "memory");
+}
+// Two doubles loaded and waited for in one block (the rare boundary lanes),
+// so the compiler sees no load in flight.
+__device__ inline void load2_now(const double *a, const double *b, double &va, double &vb) {
+    asm volatile("global_load_dwordx2 %0, %2, off\n\tglobal_load_dwordx2 %1, %3, off\n\ts_waitcnt vmcnt(0)"
+                 : "=&v"(va), "=&v"(vb) : "v"(a), "v"(b) : "memory");
+}
+
+constexpr unsigned kDropped = 0x80000000u;   // buffer offset past every resource: the store is dropped
+__device__ inline __amdgpu_buffer_rsrc_t buffer_of(void *base, long bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
+}
+// Two doubles to byte offset `off` of a buffer; AUX = 16: agent-coherent (sc1).
+template <int AUX>
+__device__ inline void store16(__amdgpu_buffer_rsrc_t r, unsigned off, double a, double b) {
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    const v4u d = {(unsigned)ua, (unsigned)(ua >> 32), (unsigned)ub, (unsigned)(ub >> 32)};
+    __builtin_amdgcn_raw_buffer_store_b128(d, r, off, 0, AUX);
+}
+
+__device__ inline int ilog2(int v) { return 31 - __builtin_clz(v); }
+
 template <int Q, int BS>
+__device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab &S, const StepIO &io, int ntiles,
+                                                                int wg, unsigned nwg, unsigned char *lds,
+                                                                double *s_tmp, int *s_flag, double *s_ivdt,
+                                                                double *s_mu, double *s_w) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int J = S.J, N = S.N, G = S.G, NG = N * G, nh = N / 2, R = 2 * G;
+    const WbShape sh = wb_shape(NG);
+    const int lc = sh.lc, cpw = sh.cpw;
+    const int cw = lane / lc, li = lane % lc;
+    constexpr int W = BS / 64;
+    const int cpt = W * cpw;
+    const int lgN = ilog2(N), lgG = ilog2(G);
+    unsigned char *A = lds + (size_t)wave * WbStage<Q>::kBytes;
+    const double2 *Pv = reinterpret_cast<const double2 *>(A + WbStage<Q>::kP);
+    const double2 *Ev = reinterpret_cast<const double2 *>(A + WbStage<Q>::kE);
+    const unsigned *Ed = reinterpret_cast<const unsigned *>(A + WbStage<Q>::kE);
+    const double *Cd = reinterpret_cast<const double *>(A + WbStage<Q>::kC);
+    const cplx *Mv = reinterpret_cast<const cplx *>(A + WbStage<Q>::kM);
+    cplx *Zcell = reinterpret_cast<cplx *>(A + WbStage<Q>::kB) + (size_t)cw * R;
+    cplx *Tcell = reinterpret_cast<cplx *>(A + WbStage<Q>::kT) + (size_t)cw * 2 * R;
+    // per-cell data, in doubles: q [cpw][G][4], phi [cpw][G][4], Sigma_s
+    // [cpw][G][G], Sigma_t [cpw][G], dx [cpw]
+    const int c_phi = cpw * 4 * G, c_ss = 2 * c_phi, c_st = c_ss + cpw * G * G, c_dx = c_st + cpw * G;
+    const int c_dw = 2 * (c_dx + cpw);
+    const int nC = (c_dw + 63) >> 6;
+    const int m_words = cpw * 4 * G * G;       // 16-byte words of the wave's rows
+    const int nM = (m_words + 63) >> 6;
+    const int lgM = 2 + 2 * lgG;               // log2(4 G^2)
+    const int tile0 = (int)(((long)ntiles * wg) / nwg);
+    const int tile1 = (int)(((long)ntiles * (wg + 1)) / nwg);
+    for (int g = tid; g < G; g += BS) s_ivdt[g] = 1.0 / (S.speed[g] * S.dt);
+    for (int m = tid; m < N; m += BS) { s_mu[m] = S.mu[m]; s_w[m] = S.w[m]; }
+    __syncthreads();
+    const size_t ehalf = (size_t)J * NG * 2;
+    const bool rb = S.ordering == 1;
+    const int nhalf = rb ? 2 : 1;
+    double e_prev = __builtin_nan("");
+    const int base = S.ctl->base;
+    const cplx *Wb = reinterpret_cast<const cplx *>(S.wb);
+    for (int l = 0;; ++l) {
+        const int cur = (base + l) & 1;
+        const double *psi_in = S.psi[cur];
+        const double *phi_in = S.phi[cur];
+        double *e_out = S.edge + (size_t)(l & 1) * ehalf;
+        const double *e_in = S.edge + (size_t)((l + 1) & 1) * ehalf;
+        const __amdgpu_buffer_rsrc_t r_edge = buffer_of(e_out, (long)ehalf * 8);
+        const __amdgpu_buffer_rsrc_t r_phi = buffer_of(S.phi[cur ^ 1], (long)J * G * 32);
+        const __amdgpu_buffer_rsrc_t r_psi = buffer_of(S.psi[cur ^ 1], (long)J * NG * 32);
+        const double *qsrc = io.q ? io.q : phi_in;   // any [J][G][4] array when there is no source
+        double dsq = 0.0;
+        bool fin = false;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1 && !fin) break;
+            // stores per tile, in issue order: the scalar flux (pass 0), then
+            // the corners (pass 0: one per pair; pass 1: the whole iterate,
+            // two per pair)
+            const int s_phi = pass == 0 ? 1 : 0, s_x = pass == 0 ? Q : 2 * Q;
+            for (int half = 0; half < nhalf; ++half) {
+                const bool from_iterate = l == 0 && half == 0;
+                const double *edges = half == 1 ? e_out : e_in;
+                const int nPEC = Q + (from_iterate ? 4 * Q : Q) + nC;
+                auto cell_of = [&](int tile, int c) {
+                    const int cc = tile * cpt + wave * cpw + c;
+                    return rb ? 2 * cc + half : cc;
+                };
+                // stage psi_{k-1/2}, the upstream corners and the per-cell data of a tile
+                auto stage_inputs = [&](int tile) {
+                    const int jc = cell_of(tile, cw);
+                    const int jj = jc < J ? jc : J - 1;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const int i0 = li + q * lc;
+                        const int i = (jc < J && i0 < NG) ? i0 : 0;
+                        const int g = i >> lgN, m = i & (N - 1);
+                        const size_t row = ((size_t)jj * G + g) * N + m;
+                        stage16<false>(S.psi_prev + row * 2, A + WbStage<Q>::kP + q * 1024);
+                        size_t up = row;   // no upstream cell: any address in the slab
+                        if (m >= nh) {
+                            if (jj > 0) up = row - NG;
+                            else if (S.periodic) up = row + (size_t)(J - 1) * NG;
+                        } else {
+                            if (jj < J - 1) up = row + NG;
+                            else if (S.periodic) up = row - (size_t)(J - 1) * NG;
+                        }
+                        if (!from_iterate) {
+                            stage16<true>(edges + up * 2, A + WbStage<Q>::kE + q * 1024);
+                        } else {   // the corner of the first iterate: dwords of psi[up][c], psi[up][c + 2]
+                            const unsigned *p = reinterpret_cast<const unsigned *>(psi_in + up * 4 + (m >= nh ? 1 : 0));
+                            unsigned char *e = A + WbStage<Q>::kE + q * 1024;
+                            stage4(p, e);
+                            stage4(p + 1, e + 256);
+                            stage4(p + 4, e + 512);
+                            stage4(p + 5, e + 768);
+                        }
+                    }
+                    for (int k = 0; k < nC; ++k) {
+                        const int d = k * 64 + lane;   // dword of the per-cell data
+                        const unsigned *src = reinterpret_cast<const unsigned *>(S.dx);
+                        if (d < 2 * c_phi) {
+                            const int c = d >> (3 + lgG), j = cell_of(tile, c);
+                            src = reinterpret_cast<const unsigned *>(qsrc + (size_t)(j < J ? j : J - 1) * G * 4) +
+                                  (d & (8 * G - 1));
+                        } else if (d < 2 * c_ss) {
+                            const int e = d - 2 * c_phi, c = e >> (3 + lgG), j = cell_of(tile, c);
+                            src = reinterpret_cast<const unsigned *>(phi_in + (size_t)(j < J ? j : J - 1) * G * 4) +
+                                  (e & (8 * G - 1));
+                        } else if (d < 2 * c_st) {
+                            const int e = d - 2 * c_ss, c = e >> (1 + 2 * lgG), j = cell_of(tile, c);
+                            src = reinterpret_cast<const unsigned *>(S.sigma_s + (size_t)(j < J ? j : J - 1) * G * G) +
+                                  (e & (2 * G * G - 1));
+                        } else if (d < 2 * c_dx) {
+                            const int e = d - 2 * c_st, c = e >> (1 + lgG), j = cell_of(tile, c);
+                            src = reinterpret_cast<const unsigned *>(S.sigma_t + (size_t)(j < J ? j : J - 1) * G) +
+                                  (e & (2 * G - 1));
+                        } else if (d < c_dw) {
+                            const int e = d - 2 * c_dx, c = e >> 1, j = cell_of(tile, c);
+                            src = reinterpret_cast<const unsigned *>(S.dx + (j < J ? j : J - 1)) + (e & 1);
+                        }
+                        stage4(src, A + WbStage<Q>::kC + k * 256);
+                    }
+                };
+                // stage the rows of (I - W C)^-1 of a tile's cells
+                auto stage_rows = [&](int tile) {
+                    for (int k = 0; k < nM; ++k) {
+                        const int d = k * 64 + lane;
+                        const cplx *src = Wb;
+                        if (d < m_words) {
+                            const int j = cell_of(tile, d >> lgM);
+                            src = Wb + (size_t)(j < J ? j : J - 1) * 2 * R * R + (d & ((1 << lgM) - 1));
+                        }
+                        stage16<false>(src, A + WbStage<Q>::kM + k * 1024);
+                    }
+                };
+                if (tile0 < tile1) {
+                    stage_inputs(tile0);
+                    stage_rows(tile0);
+                }
+                for (int tile = tile0; tile < tile1; ++tile) {
+                    const bool first = tile == tile0, more = tile + 1 < tile1;
+                    const int j = cell_of(tile, cw);
+                    const bool cell = j < J;
+                    // (1) the staged inputs of this tile have landed: after them
+                    //     came the rows (nM) and, but on the first tile, the
+                    //     previous tile's stores
+                    vm_wait(first ? nM : s_phi + nM + s_x);
+                    const double dx = Cd[c_dx + cw];
+                    cplx z[Q][2], e2[Q], e3[Q];
+                    cplx mom[Q][2];
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const int i = li + q * lc;
+                        const bool act = cell && i < NG;
+                        const int g = act ? i >> lgN : 0, m = act ? i & (N - 1) : 0;
+                        const double mu = s_mu[m];
+                        const double2 pp = Pv[q * 64 + lane];
+                        double ek, eh;
+                        if (!from_iterate) {
+                            const double2 ev = Ev[q * 64 + lane];
+                            ek = ev.x;
+                            eh = ev.y;
+                        } else {
+                            const unsigned *e = Ed + q * 256 + lane;
+                            ek = __hiloint2double((int)e[64], (int)e[0]);
+                            eh = __hiloint2double((int)e[192], (int)e[128]);
+                        }
+                        const bool up_in = m >= nh ? (j > 0 || S.periodic) : (j < J - 1 || S.periodic);
+                        if (!up_in) {   // the slab's boundary: incident flux, or vacuum
+                            const double *inc = m >= nh ? io.inc_l : io.inc_r;
+                            const int mi = m >= nh ? m - nh : m;
+                            ek = eh = 0.0;
+                            if (act && inc) load2_now(inc + (size_t)g * nh + mi, inc + ((size_t)G + g) * nh + mi, ek, eh);
+                        }
+                        const double ivdt = s_ivdt[g];
+                        const double ht = 0.5 * dx * ivdt;
+                        double b0 = ht * pp.x, b1 = ht * pp.y, b2 = 0.0, b3 = 0.0;
+                        if (io.q) {
+                            const double *qq = Cd + (cw * G + g) * 4;
+                            const double q4 = 0.25 * dx;
+                            b0 += q4 * qq[0];
+                            b1 += q4 * qq[1];
+                            b2 = q4 * qq[2];
+                            b3 = q4 * qq[3];
+                        }
+                        if (m >= nh) {
+                            b0 += mu * ek;
+                            b2 += mu * eh;
+                        } else {
+                            b1 -= mu * ek;
+                            b3 -= mu * eh;
+                        }
+                        corner_inverse(mu, dx * Cd[c_st + cw * G + g], dx * ivdt, e2[q], e3[q]);
+                        corner_apply(e2[q], e3[q], cplx{b0, -b1}, cplx{b2, -b3}, z[q][0], z[q][1]);
+                        const double w = act ? s_w[m] : 0.0;
+                        mom[q][0] = cscale(w, z[q][0]);
+                        mom[q][1] = cscale(w, z[q][1]);
+                    }
+                    // the previous scalar flux of this lane's (g, level), for the
+                    // norm, and its row of Sigma_s, read before the restaging
+                    double2 fprev{0.0, 0.0};
+                    double ssr[4] = {0.0, 0.0, 0.0, 0.0};
+                    if (li < R) {
+                        if (pass == 0) fprev = *reinterpret_cast<const double2 *>(Cd + c_phi + cw * 4 * G + 2 * li);
+                        const double *ss = Cd + c_ss + (cw * G + (li >> 1)) * G;
+#pragma unroll
+                        for (int gp = 0; gp < 4; ++gp)
+                            if (gp < G) ssr[gp] = ss[gp];
+                    }
+                    lds_reads_done();
+                    // (2) the staged inputs are consumed: stage the next tile's
+                    if (more) stage_inputs(tile + 1);
+                    // (3) moments: butterfly over the N lanes of each group
+#pragma unroll
+                    for (int q = 0; q < Q; ++q)
+                        for (int off = N >> 1; off > 0; off >>= 1)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                mom[q][h].re += __shfl_xor(mom[q][h].re, off, 64);
+                                mom[q][h].im += __shfl_xor(mom[q][h].im, off, 64);
+                            }
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const int i = li + q * lc;
+                        if (cell && i < NG && (i & (N - 1)) == 0) {
+                            const int g = i >> lgN;
+                            Zcell[2 * g] = mom[q][0];
+                            Zcell[2 * g + 1] = mom[q][1];
+                        }
+                    }
+                    wave_sync();
+                    // (4) t = (I - W C)^-1 V^T z from the staged rows: after
+                    //     them came the previous tile's corner stores (not on
+                    //     the first tile) and the next tile's staging
+                    vm_wait((first ? 0 : s_x) + (more ? nPEC : 0));
+                    if (cell && li < R) Tcell[li] = row_dot(Mv + ((size_t)cw << lgM) + (size_t)li * R, Zcell, R);
+                    wave_sync();
+                    // (5) C t = (dx/4) sum_g' Sigma_s[g][g'] t_g' on each level;
+                    //     the scalar flux is t itself
+                    unsigned phi_off = kDropped;
+                    double n0 = 0.0, n1 = 0.0;
+                    if (cell && li < R) {
+                        const int g = li >> 1, kk = li & 1;
+                        cplx ct{0.0, 0.0};
+#pragma unroll
+                        for (int gp = 0; gp < 4; ++gp)
+                            if (gp < G) ct = cadd(ct, cscale(ssr[gp], Tcell[2 * gp + kk]));
+                        const cplx t = Tcell[li];
+                        Tcell[R + li] = cscale(0.25 * dx, ct);
+                        n0 = t.re;
+                        n1 = -t.im;
+                        if (pass == 0) {
+                            phi_off = (unsigned)((((size_t)j * G + g) * 4 + 2 * kk) * 8);
+                            dsq += (n0 - fprev.x) * (n0 - fprev.x) + (n1 - fprev.y) * (n1 - fprev.y);
+                        }
+                    }
+                    if (pass == 0) store16<0>(r_phi, phi_off, n0, n1);
+                    lds_reads_done();
+                    // (6) the rows are consumed: stage the next tile's
+                    if (more) stage_rows(tile + 1);
+                    wave_sync();
+                    // (7) x = z + L_c^-1 (C t)_g; the outgoing corners (the
+                    //     whole iterate after a stop)
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const int i = li + q * lc;
+                        const bool act = cell && i < NG;
+                        const int g = act ? i >> lgN : 0, m = act ? i & (N - 1) : 0;
+                        cplx sk, sh_;
+                        corner_apply(e2[q], e3[q], Tcell[R + 2 * g], Tcell[R + 2 * g + 1], sk, sh_);
+                        const cplx xk = cadd(z[q][0], sk), xh = cadd(z[q][1], sh_);
+                        const size_t row = ((size_t)j * G + g) * N + m;
+                        if (pass == 1) {
+                            const unsigned o = act ? (unsigned)(row * 32) : kDropped;
+                            store16<0>(r_psi, o, xk.re, -xk.im);
+                            store16<0>(r_psi, act ? o + 16 : kDropped, xh.re, -xh.im);
+                        } else {
+                            // the right corner travels downstream (mu > 0), else the left
+                            const unsigned o = act ? (unsigned)(row * 16) : kDropped;
+                            const bool right = m >= nh;
+                            store16<16>(r_edge, o, right ? -xk.im : xk.re, right ? -xh.im : xh.re);
+                        }
+                    }
+                    wave_sync();   // T is rewritten by the next tile
+                }
+                // red-black: the odd cells wait for every even cell's new edges
+                if (pass == 0 && rb && half == 0) {
+                    double unused = 0.0;
+                    if (!grid_sync_coherent<BS>(S, wg, nwg, 2 * l, 0.0, s_flag, s_tmp, &unused)) return;
+                }
+            }
+            if (pass == 1) break;
+            const double wg_sum = block_sum_t<BS>(dsq, s_tmp);   // valid in thread 0
+            double tot = 0.0;
+            if (!grid_sync_coherent<BS>(S, wg, nwg, rb ? 2 * l + 1 : l, wg_sum, s_flag, s_tmp, &tot)) return;
+            fin = wb_decide(S, wg, l, tot, e_prev);
+        }
+        if (fin) return;
+    }
+}
+
+template <int Q, int BS, bool STAGED>
 __global__ __launch_bounds__(BS) void k_oci_wb(Slab S, StepIO io, int ntiles) {
-    __shared__ __align__(16) cplx s_lds[(BS / 64) * (WbLds<Q>::kA + WbLds<Q>::kB)];
     __shared__ double s_tmp[BS / 64 + 1];
     __shared__ int s_flag[4];
     __shared__ double s_ivdt[kWbMaxG];
     __shared__ double s_mu[kWbMaxN], s_w[kWbMaxN];
-    wb_body<Q, BS>(S, io, ntiles, blockIdx.x, gridDim.x, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+    if constexpr (STAGED) {
+        __shared__ __align__(16) unsigned char s_lds[(BS / 64) * WbStage<Q>::kBytes];
+        wb_body_staged<Q, BS>(S, io, ntiles, blockIdx.x, gridDim.x, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+    } else {
+        __shared__ __align__(16) cplx s_lds[(BS / 64) * (WbLds<Q>::kA + WbLds<Q>::kB)];
+        wb_body<Q, BS>(S, io, ntiles, blockIdx.x, gridDim.x, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+    }
 }
 
 // Many slabs in one persistent launch: slab k owns the workgroups
 // [wg0, wg0 + nwg) and runs the structured body on its own control block,
 // barrier words and partial sums, so slabs converge independently (the
-// structured counterpart of the dense batched kernel).
-template <int BS>
+// structured counterpart of the dense batched kernel).  STAGED: every slab
+// has a staged shape.
+template <int BS, bool STAGED>
 __global__ __launch_bounds__(BS) void k_wb_batch(const BatchEntry *tab, int nslab) {
-    __shared__ __align__(16) cplx s_lds[(BS / 64) * (WbLds<2>::kA + WbLds<2>::kB)];
     __shared__ double s_tmp[BS / 64 + 1];
     __shared__ int s_flag[4];
     __shared__ double s_ivdt[kWbMaxG];
@@ -494,36 +917,58 @@ __global__ __launch_bounds__(BS) void k_wb_batch(const BatchEntry *tab, int nsla
     const BatchEntry &e = tab[__builtin_amdgcn_readfirstlane(s_k)];
     const int lw = (int)blockIdx.x - e.wg0;
     if (lw < 0 || lw >= e.nwg) return;
-    if (e.S.N * e.S.G > 64)
-        wb_body<2, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
-    else
-        wb_body<1, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+    if constexpr (STAGED) {
+        __shared__ __align__(16) unsigned char s_lds[(BS / 64) * WbStage<2>::kBytes];
+        if (e.S.N * e.S.G > 64)
+            wb_body_staged<2, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+        else
+            wb_body_staged<1, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+    } else {
+        __shared__ __align__(16) cplx s_lds[(BS / 64) * (WbLds<2>::kA + WbLds<2>::kB)];
+        if (e.S.N * e.S.G > 64)
+            wb_body<2, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+        else
+            wb_body<1, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+    }
 }
 
 constexpr int kWbBlock = 256;
 
-hipError_t wb_batch_occupancy(int *blocks) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)&k_wb_batch<kWbBlock>, kWbBlock, 0);
+bool wb_staged(long J, int N, int G) { return wb_staged_shape(J, N, G); }
+
+hipError_t wb_batch_occupancy(bool staged, int *blocks) {
+    const void *f = staged ? (const void *)&k_wb_batch<kWbBlock, true> : (const void *)&k_wb_batch<kWbBlock, false>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, kWbBlock, 0);
 }
 
-hipError_t launch_wb_batch(const BatchEntry *tab, int nslab, int nwg, hipStream_t st) {
-    hipLaunchKernelGGL((k_wb_batch<kWbBlock>), dim3(nwg), dim3(kWbBlock), 0, st, tab, nslab);
+hipError_t launch_wb_batch(const BatchEntry *tab, int nslab, int nwg, bool staged, hipStream_t st) {
+    if (staged)
+        hipLaunchKernelGGL((k_wb_batch<kWbBlock, true>), dim3(nwg), dim3(kWbBlock), 0, st, tab, nslab);
+    else
+        hipLaunchKernelGGL((k_wb_batch<kWbBlock, false>), dim3(nwg), dim3(kWbBlock), 0, st, tab, nslab);
     return hipGetLastError();
 }
 
 int wb_cells_per_tile(int N, int G) { return (kWbBlock / 64) * wb_shape(N * G).cpw; }
 int wb_block() { return kWbBlock; }
 
-hipError_t wb_occupancy(int N, int G, int *blocks) {
-    const void *f = N * G > 64 ? (const void *)&k_oci_wb<2, kWbBlock> : (const void *)&k_oci_wb<1, kWbBlock>;
+hipError_t wb_occupancy(int N, int G, bool staged, int *blocks) {
+    const bool two = N * G > 64;
+    const void *f = staged ? (two ? (const void *)&k_oci_wb<2, kWbBlock, true> : (const void *)&k_oci_wb<1, kWbBlock, true>)
+                           : (two ? (const void *)&k_oci_wb<2, kWbBlock, false> : (const void *)&k_oci_wb<1, kWbBlock, false>);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, kWbBlock, 0);
 }
 
-hipError_t launch_oci_wb(const Slab &S, const StepIO &io, int nwg, int ntiles, hipStream_t st) {
-    if (S.N * S.G > 64)
-        hipLaunchKernelGGL((k_oci_wb<2, kWbBlock>), dim3(nwg), dim3(kWbBlock), 0, st, S, io, ntiles);
+hipError_t launch_oci_wb(const Slab &S, const StepIO &io, int nwg, int ntiles, bool staged, hipStream_t st) {
+    const bool two = S.N * S.G > 64;
+    if (staged && two)
+        hipLaunchKernelGGL((k_oci_wb<2, kWbBlock, true>), dim3(nwg), dim3(kWbBlock), 0, st, S, io, ntiles);
+    else if (staged)
+        hipLaunchKernelGGL((k_oci_wb<1, kWbBlock, true>), dim3(nwg), dim3(kWbBlock), 0, st, S, io, ntiles);
+    else if (two)
+        hipLaunchKernelGGL((k_oci_wb<2, kWbBlock, false>), dim3(nwg), dim3(kWbBlock), 0, st, S, io, ntiles);
     else
-        hipLaunchKernelGGL((k_oci_wb<1, kWbBlock>), dim3(nwg), dim3(kWbBlock), 0, st, S, io, ntiles);
+        hipLaunchKernelGGL((k_oci_wb<1, kWbBlock, false>), dim3(nwg), dim3(kWbBlock), 0, st, S, io, ntiles);
     return hipGetLastError();
 }
 

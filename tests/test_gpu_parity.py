@@ -475,6 +475,35 @@ def test_structured_converges_to_oracle(name):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("name", ["homogeneous64_n32", "regions512_n64", "multigroup192_n128",
+                                  "multigroup128_n256", "multigroup40_n512", "single_cell", "rosa_S16_dt0.1"])
+@pytest.mark.parametrize("max_wg", [None, "2"])
+def test_structured_staged_and_direct_bodies_agree(name, max_wg, monkeypatch):
+    """The staged iteration body (tile inputs staged into LDS one tile ahead)
+    and the direct body give the same lock-step iterates, both at the oracle's
+    1e-12; with two workgroups every workgroup pipelines many tiles."""
+    p, steps = CASES[name]
+    K = 7
+    if max_wg:
+        monkeypatch.setenv("OCI_MAX_WG", max_wg)
+    _announce(name, p, f"structured staged vs direct, K={K}, max_wg={max_wg}")
+    want = oracle.Oracle(p).run("oci", steps=steps, fixed_iters=K)
+    out = []
+    for direct in ("0", "1"):
+        monkeypatch.setenv("OCI_WB_DIRECT", direct)
+        s = B.Solver(p, precision=B.OCI_FP64, fixed_iters=K, solver=B.OCI_SOLVE_STRUCTURED)
+        assert s.config()["local"] == (1 if direct == "0" else 0)
+        got, infos = s.run(steps=steps, want_psi=True)
+        psi = s.psi.cpu().numpy()
+        s.close()
+        assert all(i["iterations"] == K and i["status"] == 0 for i in infos), infos
+        assert rel(got, want["phi"]) <= 1e-12
+        assert rel(psi, want["psi_iter"]) <= 1e-12
+        out.append((got, psi))
+    assert rel(out[0][0], out[1][0]) <= 1e-13
+    assert rel(out[0][1], out[1][1]) <= 1e-13
+
+
 def test_structured_iteration_counts_match_oracle():
     p = W.config("homogeneous64")
     _announce("homogeneous64", p, "structured converged, 10 steps, tol 1e-10: iteration counts")
