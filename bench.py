@@ -410,7 +410,7 @@ def run_batch_graph(probs, K, W_, tol, torch, B, precision, solver=0, ordering=0
     bs.bind_steps(K)
     for _ in range(max(W_, 1)):
         bs.step()
-    bs.rebalance()             # workgroups per slab from the measured iteration counts
+        bs.rebalance()         # workgroups per slab from the last step's iterations (and device times)
     for k in range(len(probs)):
         bs.set_state(k, None)
     bs.bind_steps(K)           # fresh argument sets, graph step i writes set i

@@ -375,11 +375,15 @@ int oci_batch_replay(oci_batch *b);
 int oci_batch_set_state(oci_batch *b, int32_t k, const double *psi_prev_dev);
 int oci_batch_get_state(const oci_batch *b, int32_t k, double *psi_prev_dev);
 
-/* Batch autotuning: re-size every slab's block of workgroups in proportion
- * to J x (4NG)^2 x (iterations of the last step enqueued, read from its
- * argument set's info records), so slabs that converge slowly get more of
- * the launch.  OCI_ERR_INVALID before any step.  Synchronises the stream; a
- * captured graph is discarded (capture again afterwards). */
+/* Batch autotuning: re-size every slab's block of workgroups from the
+ * iterations of the last step enqueued (read from its argument set's info
+ * records): a slab's time is modelled as iterations x (tiles per workgroup x
+ * cost of a tile + one grid barrier), and the blocks are chosen to minimise
+ * the largest slab time within the co-resident capacity, so slabs that
+ * converge slowly get more of the launch.  Before any rebalance the blocks
+ * follow the tile counts alone.  OCI_ERR_INVALID before any step.
+ * Synchronises the stream; a captured graph is discarded (capture again
+ * afterwards). */
 int oci_batch_rebalance(oci_batch *b);
 
 /* Launch geometry: total workgroups and, if nwg_per_slab is not NULL, the

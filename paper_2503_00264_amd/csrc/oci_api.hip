@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -833,7 +834,19 @@ extern "C" int oci_batch_destroy(oci_batch *b) {
 
 // Workgroups per slab in proportion to `weight`, at least one, at most the
 // slab's tile count, all co-resident (at most occupancy x CUs in total).
-static int batch_allocate(oci_batch *b, const std::vector<double> &weight) {
+// Workgroups per slab for one launch.  A slab's time is about its iterations
+// x (tiles per workgroup x cost of a tile + the grid barrier), so the blocks
+// are sized to minimise the largest such time (binary search on the time;
+// each slab then takes the fewest workgroups that meet it), within the
+// co-resident capacity and at least one and at most one per tile a slab.
+// its[k]: iterations of slab k's last step (1 before any step).  Tile cost:
+// the structured solve, measured when `ticks` holds each slab's device time of
+// that step (the time per iteration, less a 5 us barrier, over the tiles per
+// workgroup it had), else pairs per lane (1 or 2) with the barrier worth 1.5
+// tiles; the dense solve, the inverse rows streamed per tile (cells x n^2),
+// barrier negligible.
+static int batch_allocate(oci_batch *b, const std::vector<double> &its,
+                          const std::vector<double> &ticks = std::vector<double>()) {
     const int nslab = b->nslab;
     const int num_cu = b->slabs[0]->num_cu;
     long cap = (long)b->occ * num_cu;
@@ -841,28 +854,72 @@ static int batch_allocate(oci_batch *b, const std::vector<double> &weight) {
     if (nslab > cap) return OCI_ERR_UNSUPPORTED;
     const int bs = batch_block();
     std::vector<long> ntile(nslab), alloc(nslab);
-    double wsum = 0.0;
+    std::vector<double> cost(nslab);
+    double cmax = 0.0;
     for (int k = 0; k < nslab; ++k) {
         const oci_handle *h = b->slabs[k];
         const int rpt = h->np > bs ? h->np / bs : 1;
         const int cpt = b->structured ? wb_cells_per_tile(h->d.N, h->d.G) : bs / (h->np / rpt);
         const long cells = h->S.ordering == OCI_ORDER_RED_BLACK ? (h->d.J + 1) / 2 : h->d.J;
         ntile[k] = (cells + cpt - 1) / cpt;
-        wsum += weight[k];
+        cost[k] = b->structured ? (h->d.N * h->d.G > 64 ? 2.0 : 1.0) : (double)cpt * h->np * h->np;
+        if (cost[k] > cmax) cmax = cost[k];
+    }
+    double bar_abs = b->structured ? 1.5 : 0.0;
+    if (b->structured && (int)ticks.size() == nslab) {
+        constexpr double kBarTicks = 500.0;   // one grid barrier, 5 us of the 100 MHz device clock
+        bool ok = true;
+        std::vector<double> c(nslab);
+        for (int k = 0; k < nslab && ok; ++k) {
+            const long nw = b->tab[k].nwg > 0 ? b->tab[k].nwg : 1;
+            const double tpw = (double)((ntile[k] + nw - 1) / nw);
+            c[k] = (ticks[k] / its[k] - kBarTicks) / tpw;
+            ok = ticks[k] > 0.0 && c[k] > 0.0;
+        }
+        if (ok) {
+            cost = c;
+            bar_abs = kBarTicks;
+            cmax = *std::max_element(cost.begin(), cost.end());
+        }
+    }
+    for (int k = 0; k < nslab; ++k) cost[k] /= cmax;
+    const double bar = bar_abs / cmax;
+    // fewest workgroups for slab k to finish within time T (0: cannot)
+    auto need = [&](int k, double T) -> long {
+        const double per = (T / its[k] - bar) / cost[k];   // tiles per workgroup allowed
+        if (per < 1.0) return 0;
+        const long p = per >= (double)ntile[k] ? ntile[k] : (long)per;
+        return (ntile[k] + p - 1) / p;
+    };
+    auto time_of = [&](int k, long n) { return its[k] * (cost[k] * (double)((ntile[k] + n - 1) / n) + bar); };
+    double lo = 0.0, hi = 0.0;
+    for (int k = 0; k < nslab; ++k) hi = std::max(hi, time_of(k, 1));
+    for (int it = 0; it < 100; ++it) {
+        const double T = 0.5 * (lo + hi);
+        long total = 0;
+        bool ok = true;
+        for (int k = 0; k < nslab && ok; ++k) {
+            const long n = need(k, T);
+            if (n == 0) ok = false;
+            total += n;
+        }
+        if (ok && total <= cap) hi = T; else lo = T;
     }
     long used = 0;
     for (int k = 0; k < nslab; ++k) {
-        long a = (long)(weight[k] / wsum * (double)cap);
-        if (a < 1) a = 1;
-        if (a > ntile[k]) a = ntile[k];
-        alloc[k] = a;
-        used += a;
+        alloc[k] = need(k, hi);
+        if (alloc[k] < 1) alloc[k] = 1;
+        used += alloc[k];
     }
-    while (used > cap) {   // trim the largest allocations
-        int kmax = 0;
-        for (int k = 1; k < nslab; ++k) if (alloc[k] > alloc[kmax]) kmax = k;
-        --alloc[kmax];
-        --used;
+    // spare workgroups to the slowest slabs while that shortens them
+    while (used < cap) {
+        int kmax = -1;
+        double tmax = -1.0;
+        for (int k = 0; k < nslab; ++k)
+            if (alloc[k] < ntile[k] && time_of(k, alloc[k]) > tmax) { tmax = time_of(k, alloc[k]); kmax = k; }
+        if (kmax < 0 || time_of(kmax, alloc[kmax] + 1) >= tmax) break;
+        ++alloc[kmax];
+        ++used;
     }
     int wg0 = 0;
     const int nsets = b->nbound > 0 ? b->nbound : 1;
@@ -932,15 +989,7 @@ extern "C" int oci_batch_setup(int32_t nslab, const oci_desc *descs, void *works
         memset(&b->tab[k], 0, sizeof(BatchEntry));
         b->tab[k].S = b->slabs[k]->S;
     }
-    std::vector<double> wgt(nslab);
-    for (int k = 0; k < nslab; ++k) {
-        const oci_handle *h = b->slabs[k];
-        // bytes per iteration: the factor stream, or for the structured solve
-        // the per-(g, m) sources and edges and the per-cell capacitance rows
-        wgt[k] = b->structured ? (double)h->d.J * (64.0 * h->d.N * h->d.G + 128.0 * h->d.G * h->d.G)
-                               : (double)h->d.J * h->np * h->np;
-    }
-    rc = batch_allocate(b, wgt);
+    rc = batch_allocate(b, std::vector<double>(nslab, 1.0));
     if (rc) { oci_batch_destroy(b); return rc; }
     *out = b;
     return OCI_OK;
@@ -1042,14 +1091,17 @@ extern "C" int oci_batch_rebalance(oci_batch *b) {
     HIPCHECK(hipStreamSynchronize(b->st));
     HIPCHECK(hipMemcpy(info.data(), b->info_dev + (size_t)b->last * b->nslab, sizeof(oci_step_info) * b->nslab,
                        hipMemcpyDeviceToHost));
-    std::vector<double> wgt(b->nslab);
-    for (int k = 0; k < b->nslab; ++k) {
-        const oci_handle *h = b->slabs[k];
-        const int its = info[k].iterations > 0 ? info[k].iterations : 1;
-        wgt[k] = (b->structured ? (double)h->d.J * (64.0 * h->d.N * h->d.G + 128.0 * h->d.G * h->d.G)
-                                : (double)h->d.J * h->np * h->np) * its;
+    std::vector<double> its(b->nslab), ticks;
+    for (int k = 0; k < b->nslab; ++k) its[k] = info[k].iterations > 0 ? info[k].iterations : 1;
+    if (b->structured) {   // each slab's device time of that step
+        ticks.resize(b->nslab);
+        for (int k = 0; k < b->nslab; ++k) {
+            Ctl c;
+            HIPCHECK(hipMemcpy(&c, b->slabs[k]->S.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+            ticks[k] = c.t_end > c.t_begin ? (double)(c.t_end - c.t_begin) : 0.0;
+        }
     }
-    const int rc = batch_allocate(b, wgt);
+    const int rc = batch_allocate(b, its, ticks);
     if (rc) return rc;
     HIPCHECK(batch_upload(b));
     if (b->graph) { (void)hipGraphExecDestroy(b->graph); b->graph = nullptr; }

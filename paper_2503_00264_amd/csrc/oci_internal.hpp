@@ -54,7 +54,8 @@ struct Ctl {
     double rho;            // e_l / e_{l-1}
     int32_t bcast;         // batched steps: start the next step from psi_prev on both levels
     int32_t pad0;
-    double pad[2];
+    uint64_t t_begin;      // structured solve: device clock (wall_clock64) at the step's start and
+    uint64_t t_end;        // at its stopping decision, for the batch's workgroup allocation
 };
 static_assert(sizeof(Ctl) == 80, "Ctl layout");
 

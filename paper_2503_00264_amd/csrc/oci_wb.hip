@@ -239,6 +239,7 @@ __device__ inline bool wb_decide(const Slab &S, int wg, int l, double tot, doubl
     if (S.hist && iters <= S.hist_cap && wg == 0 && threadIdx.x == 0) S.hist[iters - 1] = e;
     if (done && wg == 0 && threadIdx.x == 0) {
         Ctl *c = S.ctl;
+        c->t_end = wall_clock64();
         c->iter = iters;
         c->e_last = e;
         c->rho = rho;
@@ -274,6 +275,7 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
     const int tile1 = (int)(((long)ntiles * (wg + 1)) / nwg);
     for (int g = tid; g < G; g += BS) s_ivdt[g] = 1.0 / (S.speed[g] * S.dt);
     for (int m = tid; m < N; m += BS) { s_mu[m] = S.mu[m]; s_w[m] = S.w[m]; }
+    if (wg == 0 && tid == 0) S.ctl->t_begin = wall_clock64();
     __syncthreads();
     // outgoing corners of iteration l go to the compact edge buffer of parity
     // l, through coherent stores (other workgroups read them after the grid
@@ -496,7 +498,7 @@ __host__ __device__ inline bool wb_staged_shape(long J, int N, int G) {
     if (NG > 128) return false;
     const WbShape sh = wb_shape(NG);
     if (sh.cpw * 4 * G * G > 128) return false;                          // rows: 128 complex words
-    if (sh.cpw * (16 * G + 2 * G * G + 2 * G + 2) > 256) return false;   // per-cell data: 256 dwords
+    if (sh.cpw * G > 8 || sh.cpw > 8) return false;                      // per-cell data: four 64-dword loads
     return J * NG * 32 < (1L << 31);                                     // 32-bit buffer offsets
 }
 
@@ -599,11 +601,12 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
     const cplx *Mv = reinterpret_cast<const cplx *>(A + WbStage<Q>::kM);
     cplx *Zcell = reinterpret_cast<cplx *>(A + WbStage<Q>::kB) + (size_t)cw * R;
     cplx *Tcell = reinterpret_cast<cplx *>(A + WbStage<Q>::kT) + (size_t)cw * 2 * R;
-    // per-cell data, in doubles: q [cpw][G][4], phi [cpw][G][4], Sigma_s
-    // [cpw][G][G], Sigma_t [cpw][G], dx [cpw]
-    const int c_phi = cpw * 4 * G, c_ss = 2 * c_phi, c_st = c_ss + cpw * G * G, c_dx = c_st + cpw * G;
-    const int c_dw = 2 * (c_dx + cpw);
-    const int nC = (c_dw + 63) >> 6;
+    // per-cell data, one 64-dword staging load each, in doubles: q
+    // [cpw][G][4] at 0, phi [cpw][G][4] at 32, Sigma_s [cpw][G][G] at 64,
+    // Sigma_t [cpw][G] at 96, dx [cpw] at 112 (cpw G <= 8, cpw <= 8)
+    constexpr int c_phi = 32, c_ss = 64, c_st = 96, c_dx = 112, nC = 4;
+    // this lane's pair q (any pair of the cell for padding lanes)
+    auto pair_of = [&](int q) { return li + q * lc < NG ? li + q * lc : 0; };
     const int m_words = cpw * 4 * G * G;       // 16-byte words of the wave's rows
     const int nM = (m_words + 63) >> 6;
     const int lgM = 2 + 2 * lgG;               // log2(4 G^2)
@@ -611,6 +614,7 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
     const int tile1 = (int)(((long)ntiles * (wg + 1)) / nwg);
     for (int g = tid; g < G; g += BS) s_ivdt[g] = 1.0 / (S.speed[g] * S.dt);
     for (int m = tid; m < N; m += BS) { s_mu[m] = S.mu[m]; s_w[m] = S.w[m]; }
+    if (wg == 0 && tid == 0) S.ctl->t_begin = wall_clock64();
     __syncthreads();
     const size_t ehalf = (size_t)J * NG * 2;
     const bool rb = S.ordering == 1;
@@ -646,59 +650,57 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                 };
                 // stage psi_{k-1/2}, the upstream corners and the per-cell data of a tile
                 auto stage_inputs = [&](int tile) {
-                    const int jc = cell_of(tile, cw);
+                    // lane-dependent offsets recomputed here rather than kept
+                    // live across the tile loop (register pressure)
+                    int ln = lane;
+                    asm volatile("" : "+v"(ln));
+                    const int lcw = ln / lc, lli = ln % lc;
+                    const int jc = cell_of(tile, lcw);
                     const int jj = jc < J ? jc : J - 1;
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        const int i0 = li + q * lc;
-                        const int i = (jc < J && i0 < NG) ? i0 : 0;
-                        const int g = i >> lgN, m = i & (N - 1);
-                        const size_t row = ((size_t)jj * G + g) * N + m;
-                        stage16<false>(S.psi_prev + row * 2, A + WbStage<Q>::kP + q * 1024);
-                        size_t up = row;   // no upstream cell: any address in the slab
-                        if (m >= nh) {
+                        const int i = lli + q * lc < NG ? lli + q * lc : 0;
+                        const int row = jj * NG + i;   // (j, g, m) with i = g N + m; J NG < 2^26
+                        stage16<false>(S.psi_prev + (size_t)row * 2, A + WbStage<Q>::kP + q * 1024);
+                        const bool right = (i & (N - 1)) >= nh;
+                        int up = row;   // no upstream cell: any address in the slab
+                        if (right) {
                             if (jj > 0) up = row - NG;
-                            else if (S.periodic) up = row + (size_t)(J - 1) * NG;
+                            else if (S.periodic) up = row + (J - 1) * NG;
                         } else {
                             if (jj < J - 1) up = row + NG;
-                            else if (S.periodic) up = row - (size_t)(J - 1) * NG;
+                            else if (S.periodic) up = row - (J - 1) * NG;
                         }
                         if (!from_iterate) {
-                            stage16<true>(edges + up * 2, A + WbStage<Q>::kE + q * 1024);
+                            stage16<true>(edges + (size_t)up * 2, A + WbStage<Q>::kE + q * 1024);
                         } else {   // the corner of the first iterate: dwords of psi[up][c], psi[up][c + 2]
-                            const unsigned *p = reinterpret_cast<const unsigned *>(psi_in + up * 4 + (m >= nh ? 1 : 0));
+                            const unsigned *pc = reinterpret_cast<const unsigned *>(psi_in + (size_t)up * 4 + (right ? 1 : 0));
                             unsigned char *e = A + WbStage<Q>::kE + q * 1024;
-                            stage4(p, e);
-                            stage4(p + 1, e + 256);
-                            stage4(p + 4, e + 512);
-                            stage4(p + 5, e + 768);
+                            stage4(pc, e);
+                            stage4(pc + 1, e + 256);
+                            stage4(pc + 4, e + 512);
+                            stage4(pc + 5, e + 768);
                         }
                     }
-                    for (int k = 0; k < nC; ++k) {
-                        const int d = k * 64 + lane;   // dword of the per-cell data
-                        const unsigned *src = reinterpret_cast<const unsigned *>(S.dx);
-                        if (d < 2 * c_phi) {
-                            const int c = d >> (3 + lgG), j = cell_of(tile, c);
-                            src = reinterpret_cast<const unsigned *>(qsrc + (size_t)(j < J ? j : J - 1) * G * 4) +
-                                  (d & (8 * G - 1));
-                        } else if (d < 2 * c_ss) {
-                            const int e = d - 2 * c_phi, c = e >> (3 + lgG), j = cell_of(tile, c);
-                            src = reinterpret_cast<const unsigned *>(phi_in + (size_t)(j < J ? j : J - 1) * G * 4) +
-                                  (e & (8 * G - 1));
-                        } else if (d < 2 * c_st) {
-                            const int e = d - 2 * c_ss, c = e >> (1 + 2 * lgG), j = cell_of(tile, c);
-                            src = reinterpret_cast<const unsigned *>(S.sigma_s + (size_t)(j < J ? j : J - 1) * G * G) +
-                                  (e & (2 * G * G - 1));
-                        } else if (d < 2 * c_dx) {
-                            const int e = d - 2 * c_st, c = e >> (1 + lgG), j = cell_of(tile, c);
-                            src = reinterpret_cast<const unsigned *>(S.sigma_t + (size_t)(j < J ? j : J - 1) * G) +
-                                  (e & (2 * G - 1));
-                        } else if (d < c_dw) {
-                            const int e = d - 2 * c_dx, c = e >> 1, j = cell_of(tile, c);
-                            src = reinterpret_cast<const unsigned *>(S.dx + (j < J ? j : J - 1)) + (e & 1);
-                        }
-                        stage4(src, A + WbStage<Q>::kC + k * 256);
-                    }
+                    auto clampj = [&](int c) {
+                        const int jx = cell_of(tile, c);
+                        return jx < J ? jx : J - 1;
+                    };
+                    unsigned char *C = A + WbStage<Q>::kC;
+                    // this lane's dword of each per-cell load: (cell of the
+                    // wave, dword in the cell's record)
+                    const int cq = ln >> (3 + lgG), oq = ln & (8 * G - 1);
+                    const int cs = ln >> (1 + 2 * lgG), os = ln & (2 * G * G - 1);
+                    const bool dxl = ln >= 32;
+                    const int ct = dxl ? (ln & 31) >> 1 : (ln & 31) >> (1 + lgG);
+                    const int ot = dxl ? ln & 1 : ln & (2 * G - 1);
+                    stage4(reinterpret_cast<const unsigned *>(qsrc) + clampj(cq) * 8 * G + oq, C);
+                    stage4(reinterpret_cast<const unsigned *>(phi_in) + clampj(cq) * 8 * G + oq, C + 256);
+                    stage4(reinterpret_cast<const unsigned *>(S.sigma_s) + clampj(cs) * 2 * G * G + os, C + 512);
+                    const int jt = clampj(ct);
+                    const unsigned *pt = dxl ? reinterpret_cast<const unsigned *>(S.dx) + jt * 2 + ot
+                                             : reinterpret_cast<const unsigned *>(S.sigma_t) + jt * 2 * G + ot;
+                    stage4(pt, C + 768);
                 };
                 // stage the rows of (I - W C)^-1 of a tile's cells
                 auto stage_rows = [&](int tile) {
@@ -729,9 +731,8 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                     cplx mom[Q][2];
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        const int i = li + q * lc;
-                        const bool act = cell && i < NG;
-                        const int g = act ? i >> lgN : 0, m = act ? i & (N - 1) : 0;
+                        const bool act = cell && li + q * lc < NG;
+                        const int g = pair_of(q) >> lgN, m = pair_of(q) & (N - 1);
                         const double mu = s_mu[m];
                         const double2 pp = Pv[q * 64 + lane];
                         double ek, eh;
@@ -829,7 +830,7 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                         n0 = t.re;
                         n1 = -t.im;
                         if (pass == 0) {
-                            phi_off = (unsigned)((((size_t)j * G + g) * 4 + 2 * kk) * 8);
+                            phi_off = (unsigned)(((j * G + g) * 4 + 2 * kk) * 8);
                             dsq += (n0 - fprev.x) * (n0 - fprev.x) + (n1 - fprev.y) * (n1 - fprev.y);
                         }
                     }
@@ -842,20 +843,19 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                     //     whole iterate after a stop)
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        const int i = li + q * lc;
-                        const bool act = cell && i < NG;
-                        const int g = act ? i >> lgN : 0, m = act ? i & (N - 1) : 0;
+                        const bool act = cell && li + q * lc < NG;
+                        const int g = pair_of(q) >> lgN, m = pair_of(q) & (N - 1);
                         cplx sk, sh_;
                         corner_apply(e2[q], e3[q], Tcell[R + 2 * g], Tcell[R + 2 * g + 1], sk, sh_);
                         const cplx xk = cadd(z[q][0], sk), xh = cadd(z[q][1], sh_);
-                        const size_t row = ((size_t)j * G + g) * N + m;
+                        const unsigned row = (unsigned)(j * NG + pair_of(q));
                         if (pass == 1) {
-                            const unsigned o = act ? (unsigned)(row * 32) : kDropped;
+                            const unsigned o = act ? row * 32 : kDropped;
                             store16<0>(r_psi, o, xk.re, -xk.im);
                             store16<0>(r_psi, act ? o + 16 : kDropped, xh.re, -xh.im);
                         } else {
                             // the right corner travels downstream (mu > 0), else the left
-                            const unsigned o = act ? (unsigned)(row * 16) : kDropped;
+                            const unsigned o = act ? row * 16 : kDropped;
                             const bool right = m >= nh;
                             store16<16>(r_edge, o, right ? -xk.im : xk.re, right ? -xh.im : xh.re);
                         }
@@ -878,8 +878,11 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
     }
 }
 
+// Waves per SIMD asked of the compiler: four for one pair per lane, three
+// for two (the register budgets 128 and 168 the bodies fit without spills).
 template <int Q, int BS, bool STAGED>
-__global__ __launch_bounds__(BS) void k_oci_wb(Slab S, StepIO io, int ntiles) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(Q == 1 ? 4 : 3))) void k_oci_wb(Slab S, StepIO io,
+                                                                                                int ntiles) {
     __shared__ double s_tmp[BS / 64 + 1];
     __shared__ int s_flag[4];
     __shared__ double s_ivdt[kWbMaxG];
@@ -898,8 +901,11 @@ __global__ __launch_bounds__(BS) void k_oci_wb(Slab S, StepIO io, int ntiles) {
 // barrier words and partial sums, so slabs converge independently (the
 // structured counterpart of the dense batched kernel).  STAGED: every slab
 // has a staged shape.
+// Three waves per SIMD (168 registers; the one- and two-pair bodies share the
+// kernel, at the price of a few spilled registers).
 template <int BS, bool STAGED>
-__global__ __launch_bounds__(BS) void k_wb_batch(const BatchEntry *tab, int nslab) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_wb_batch(const BatchEntry *tab,
+                                                                                        int nslab) {
     __shared__ double s_tmp[BS / 64 + 1];
     __shared__ int s_flag[4];
     __shared__ double s_ivdt[kWbMaxG];
