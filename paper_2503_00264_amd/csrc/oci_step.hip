@@ -1653,7 +1653,7 @@ constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 // launch ends when the last one has.
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
-void k_oci_batch(const BatchEntry *tab, int nslab) {
+void k_oci_batch(const BatchEntry *__restrict__ tab, int nslab) {
     // one workgroup runs one body: their LDS overlays
     constexpr size_t kLds = cmax(cmax(cmax(sizeof(GlobalLds<T, 8, false, BS>), sizeof(GlobalLds<T, 16, false, BS>)),
                                       cmax(sizeof(GlobalLds<T, 32, false, BS>), sizeof(GlobalLds<T, 64, false, BS>))),

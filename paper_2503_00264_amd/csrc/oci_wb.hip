@@ -904,8 +904,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(Q == 1 ? 4 :
 // Three waves per SIMD (168 registers; the one- and two-pair bodies share the
 // kernel, at the price of a few spilled registers).
 template <int BS, bool STAGED>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_wb_batch(const BatchEntry *tab,
-                                                                                        int nslab) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_wb_batch(
+    const BatchEntry *__restrict__ tab, int nslab) {
     __shared__ double s_tmp[BS / 64 + 1];
     __shared__ int s_flag[4];
     __shared__ double s_ivdt[kWbMaxG];
@@ -920,21 +920,26 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_
         s_k = lo;
     }
     __syncthreads();
+    // the table is read-only for the kernel (restrict): its fields are read
+    // with scalar loads wherever the body needs them, not with vector loads
     const BatchEntry &e = tab[__builtin_amdgcn_readfirstlane(s_k)];
+    const Slab &S = e.S;
+    const StepIO &io = e.io;
+    const int ntiles = e.ntiles, nwg = e.nwg;
     const int lw = (int)blockIdx.x - e.wg0;
-    if (lw < 0 || lw >= e.nwg) return;
+    if (lw < 0 || lw >= nwg) return;
     if constexpr (STAGED) {
         __shared__ __align__(16) unsigned char s_lds[(BS / 64) * WbStage<2>::kBytes];
-        if (e.S.N * e.S.G > 64)
-            wb_body_staged<2, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+        if (S.N * S.G > 64)
+            wb_body_staged<2, BS>(S, io, ntiles, lw, nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
         else
-            wb_body_staged<1, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+            wb_body_staged<1, BS>(S, io, ntiles, lw, nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
     } else {
         __shared__ __align__(16) cplx s_lds[(BS / 64) * (WbLds<2>::kA + WbLds<2>::kB)];
-        if (e.S.N * e.S.G > 64)
-            wb_body<2, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+        if (S.N * S.G > 64)
+            wb_body<2, BS>(S, io, ntiles, lw, nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
         else
-            wb_body<1, BS>(e.S, e.io, e.ntiles, lw, e.nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
+            wb_body<1, BS>(S, io, ntiles, lw, nwg, s_lds, s_tmp, s_flag, s_ivdt, s_mu, s_w);
     }
 }
 
