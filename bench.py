@@ -497,9 +497,9 @@ def batch_main(a, torch, B):
     K = a.steps
     J = np.array([p["J"] for p in probs])
     r = run_batch_graph(probs, K, a.warmup, a.tol, torch, B, B.OCI_FP64, B.OCI_SOLVE_STRUCTURED)
-    head = batch_graph_summary(r, probs, K, batch_structured_bytes(probs), "k_wb_batch<256>")
+    head = batch_graph_summary(r, probs, K, batch_structured_bytes(probs), "k_wb_batch<256,true>")
     roof = head.pop("roofline")
-    ratio = recorded_traffic("k_wb_batch<256>", "k_wb_batch_batch64.md", "HBM bytes per algorithmic byte",
+    ratio = recorded_traffic("k_wb_batch<256,true>", "k_wb_batch_batch64.md", "HBM bytes per algorithmic byte",
                              STRUCTURED_SOURCES)
     roof["traffic"] = None if ratio is None else round(ratio * roof["bytes_per_step"], 1)
     roof["note"] = ("algorithmic bytes of the structured solve per cell-iteration (psi_{k-1/2}, incident "
@@ -554,7 +554,7 @@ def batch_main(a, torch, B):
         torch.cuda.empty_cache()
         rr = run_batch_graph(probs, K, a.warmup, a.tol, torch, B, B.OCI_FP64, B.OCI_SOLVE_STRUCTURED,
                              B.OCI_ORDER_RED_BLACK)
-        rb = batch_graph_summary(rr, probs, K, batch_structured_bytes(probs), "k_wb_batch<256>")
+        rb = batch_graph_summary(rr, probs, K, batch_structured_bytes(probs), "k_wb_batch<256,true>")
         rb["speedup_over_jacobi"] = round(r["time_s"] / rr["time_s"], 3)
         comp["structured_red_black_batched"] = rb
     if not a.no_comparison_workloads:
