@@ -29,8 +29,9 @@ hipError_t launch_oci_local(const Slab &S, const StepIO &io, bool fp32, int np, 
                             int ntiles, size_t dyn, hipStream_t st);
 bool resident_supported(bool fp32, int np);
 bool block_supported(int bs);
+int si_loop_occupancy(const Slab &S, bool multi);
+hipError_t launch_si_loop(const Slab &S, const StepIO &io, int nwg, hipStream_t st);
 hipError_t launch_si_iteration(const Slab &S, const StepIO &io, hipStream_t st);
-size_t si_flux_blocks(const Slab &S);
 hipError_t batch_occupancy(bool fp32, int *blocks);
 int batch_block();
 hipError_t launch_batch_step(const BatchEntry *tab, int nslab, int nwg, bool fp32, bool structured, bool staged,
@@ -66,7 +67,6 @@ struct oci_handle {
     bool wb_staged;        // ... with the staged iteration body (shape permitting)
     size_t dyn_lds;        // its dynamic LDS bytes
     bool need_broadcast;   // next step starts from psi_prev on both levels
-    int32_t h_flag;        // host copy of the done flag for SI's convergence polling
     bool profiling;
     hipGraphExec_t graph;              // steps captured by oci_capture_steps
     std::vector<hipEvent_t> ev_pool;   // recorded pairs: [2k] start, [2k+1] stop
@@ -645,27 +645,57 @@ extern "C" int si_step(oci_handle *h, const double *q_dev, const double *inc_lef
     int rc = check_step_args(h, phi_out_dev, info_dev);
     if (rc) return rc;
     StepIO io{q_dev, inc_left_dev, inc_right_dev, phi_out_dev, psi_out_dev, info_dev};
-    HIPCHECK(launch_begin(h->S, io, h->need_broadcast, h->st, 0));
+    // Small problems (up to kSiOneWorkgroup (cell, group, angle) rows) run the
+    // whole iteration loop in one persistent launch on one 1024-thread
+    // workgroup (the decision stays on the device; 2.6x faster than the launch
+    // sequence at 80 rows).  Larger ones run the per-phase launch sequence,
+    // which measured faster than the persistent loop there (one or many
+    // workgroups: 1.0-1.5x slower from 3648 rows up).  OCI_SI_MODE = launches
+    // | one | many (testing) forces a layout; many = about one workgroup per
+    // 4096 rows, at most one per CU, grid barriers between the phases.
+    constexpr long kSiOneWorkgroup = 1024;
+    const long rows = (long)h->d.J * h->d.G * h->d.N;
+    int kind = rows <= kSiOneWorkgroup ? 1 : 0;
+    if (const char *m = getenv("OCI_SI_MODE")) {
+        if (!strcmp(m, "launches")) kind = 0;
+        else if (!strcmp(m, "one")) kind = 1;
+        else if (!strcmp(m, "many")) kind = 2;
+    }
+    long nwg = 1;
+    if (kind == 2) {
+        nwg = (rows + 4095) / 4096;
+        if (nwg > h->num_cu) nwg = h->num_cu;
+        if (nwg < 2) nwg = 2;
+    }
+    if (kind > 0 && si_loop_occupancy(h->S, kind == 2) < 1) return OCI_ERR_UNSUPPORTED;
+    Slab S = h->S;
+    S.bar_groups = (int)((nwg + S.bar_gsz - 1) / S.bar_gsz);   // the barrier words the launch uses
+    HIPCHECK(launch_begin(S, io, h->need_broadcast, h->st, 0));
     h->need_broadcast = false;
-    // the iterations stop themselves on the device; the host only polls the
-    // done flag between growing batches of launches
-    const int cap = h->d.fixed_iters > 0 ? h->d.fixed_iters : h->d.max_iters;
     hipEvent_t e0 = h->profiling ? prof_event(h) : nullptr, e1 = h->profiling ? prof_event(h) : nullptr;
     if (e0) HIPCHECK(hipEventRecord(e0, h->st));
-    int launched = 0, batch = 4;
-    for (;;) {
-        const int k = (cap - launched) < batch ? (cap - launched) : batch;
-        for (int i = 0; i < k; ++i) HIPCHECK(launch_si_iteration(h->S, io, h->st));
-        launched += k;
-        if (launched >= cap) break;
-        HIPCHECK(hipMemcpyAsync(&h->h_flag, &h->S.ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
-        HIPCHECK(hipStreamSynchronize(h->st));
-        if (h->h_flag) break;
-        if (batch < 64) batch *= 2;
+    if (kind > 0) {
+        HIPCHECK(launch_si_loop(S, io, (int)nwg, h->st));
+    } else {
+        // host-driven: the iterations stop themselves on the device; the host
+        // polls the done flag between growing batches of launches
+        const int cap = h->d.fixed_iters > 0 ? h->d.fixed_iters : h->d.max_iters;
+        int launched = 0, batch = 4;
+        int32_t flag = 0;
+        for (;;) {
+            const int k = (cap - launched) < batch ? (cap - launched) : batch;
+            for (int i = 0; i < k; ++i) HIPCHECK(launch_si_iteration(S, io, h->st));
+            launched += k;
+            if (launched >= cap) break;
+            HIPCHECK(hipMemcpyAsync(&flag, &S.ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+            HIPCHECK(hipStreamSynchronize(h->st));
+            if (flag) break;
+            if (batch < 64) batch *= 2;
+        }
     }
     if (e1) HIPCHECK(hipEventRecord(e1, h->st));
     if (e1) h->prof_steps += 1;
-    HIPCHECK(launch_end(h->S, io, h->st));
+    HIPCHECK(launch_end(S, io, h->st));
     return OCI_OK;
 }
 

@@ -9,6 +9,26 @@ namespace oci {
 
 constexpr int OK = 0, NOT_CONVERGED = 1, NONFINITE = 2;
 
+// The stopping rule after `iters` iterations (1, 2, ...) from the norm e of
+// the last change and e_prev of the one before (NaN for the first): a
+// non-finite e ends the step; a fixed count ends it after that many; else
+// e < tol (1 - e / e_prev) from the second iteration on (e = 0 included);
+// else the iteration cap.  Returns 1 when the step ends, with its status.
+__device__ inline int stop_rule(const Slab &S, int iters, double e, double e_prev, int *status) {
+    *status = OK;
+    if (!isfinite(e)) {
+        *status = NONFINITE;
+        return 1;
+    }
+    if (S.fixed_iters > 0) return iters >= S.fixed_iters;
+    if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - e / e_prev))) return 1;
+    if (iters >= S.max_iters) {
+        *status = NOT_CONVERGED;
+        return 1;
+    }
+    return 0;
+}
+
 // --------------------------------------------------------------- reductions
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -32,22 +32,11 @@ __device__ inline void decide(const Slab &S, double e) {
     Ctl *c = S.ctl;
     const int iters = c->iter + 1;
     const double e_prev = c->e_prev;
-    const double rho = iters >= 2 ? e / e_prev : __builtin_nan("");
-    int done = 0, status = OK;
-    if (!isfinite(e)) {
-        done = 1;
-        status = NONFINITE;
-    } else if (S.fixed_iters > 0) {
-        done = iters >= S.fixed_iters;
-    } else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - e / e_prev))) {
-        done = 1;
-    } else if (iters >= S.max_iters) {
-        done = 1;
-        status = NOT_CONVERGED;
-    }
+    int status = OK;
+    const int done = stop_rule(S, iters, e, e_prev, &status);
     c->iter = iters;
     c->e_last = e;
-    c->rho = rho;
+    c->rho = iters >= 2 ? e / e_prev : __builtin_nan("");
     c->e_prev = e;
     c->status = status;
     c->done = done;
@@ -1496,22 +1485,28 @@ __global__ __launch_bounds__(kBlock) void k_const_rhs(Slab S, StepIO io) {
 // the previous iterate.  Each (group, angle) chain is swept cell by cell, as
 // in the paper, but the work that does not depend on the incoming edge runs
 // in parallel around the serial part:
-//   k_si_pre    every cell: d = constant RHS + dx/4 sum_g' Ss phi^(l), the
-//               uncoupled solution base = L_c^-1 d and its outgoing edges
-//   k_si_sweep  one workgroup: the chains run e_out = alpha + M e_in cell by
-//               cell (M: the 2x2 edge-to-edge map of the cell), reading
-//               alpha and M from an LDS ring that the other waves fill ahead
-//               of them; the incident edge met at every cell is recorded
-//   k_si_flux   every (cell, group, corner/level): psi = base + response x
-//               incident edge, phi = sum_m w_m psi, its change, the decision
-__global__ __launch_bounds__(kBlock) void k_si_pre(Slab S) {
-    const Ctl *c = S.ctl;
-    if (c->done) return;
-    const int cur = (c->base + c->iter) & 1;
-    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+//   pre    every (cell, group, angle): d = constant RHS + dx/4 sum_g' Ss
+//          phi^(l), the uncoupled solution base = L_c^-1 d and its outgoing
+//          edges;
+//   sweep  one workgroup: the chains run e_out = alpha + M e_in cell by cell
+//          (M: the 2x2 edge-to-edge map of the cell), reading alpha and M
+//          from an LDS ring that the other waves fill ahead of them; the
+//          incident edge met at every cell is recorded;
+//   flux   every (cell, group, corner/level): psi = base + response x
+//          incident edge, phi = sum_m w_m psi, its change; then the norm and
+//          the decision.
+// The whole iteration loop of a step runs in one persistent launch
+// (k_si_loop: the decision never leaves the device), on one workgroup for
+// small problems (phases separated by workgroup barriers) or on many (grid
+// barriers with agent-scope release/acquire between the phases).  The
+// per-phase kernels (k_si_pre, k_si_sweep, k_si_flux) remain as the launch
+// sequence that a host loop can drive.
+
+// One (cell, group, angle) row of the pre pass.
+__device__ inline void si_pre_row(const Slab &S, size_t t, int cur) {
     const int N = S.N, G = S.G;
-    if (t >= (size_t)S.J * G * N) return;
-    const int m = t % N, g = (t / N) % G, j = t / ((size_t)N * G);
+    const unsigned tu = (unsigned)t, jg32 = tu / (unsigned)N;   // J G N < 2^31: 32-bit division
+    const int m = tu - jg32 * N, g = jg32 % (unsigned)G, j = jg32 / (unsigned)G;
     const size_t jg = (size_t)j * G + g;
     const double *phi_in = S.phi[cur];
     const double *cr = S.crhs + t * 4;
@@ -1536,13 +1531,11 @@ __global__ __launch_bounds__(kBlock) void k_si_pre(Slab S) {
 
 constexpr int kSweepBlock = 1024;
 
-// One workgroup.  LDS ring: [2][C][NG][6] doubles (alpha0, alpha1, M00, M01,
-// M10, M11 per chain and sweep step).  Waves at or after the first wave
-// without chains fill buffer (c+1) & 1 while the chain lanes consume c & 1.
-__global__ __launch_bounds__(kSweepBlock) void k_si_sweep(Slab S, StepIO io, int C) {
-    extern __shared__ __align__(16) double s_ring[];
-    const Ctl *ctl = S.ctl;
-    if (ctl->done) return;
+// The chain sweep, run by all kSweepBlock threads of one workgroup.  LDS
+// ring: [2][C][NG][6] doubles (alpha0, alpha1, M00, M01, M10, M11 per chain
+// and sweep step).  Waves at or after the first wave without chains fill
+// buffer (c+1) & 1 while the chain lanes consume c & 1.
+__device__ inline void si_sweep_body(const Slab &S, const StepIO &io, int C, double *s_ring) {
     const int N = S.N, G = S.G, J = S.J, NG = N * G, nh = N / 2;
     const int tid = threadIdx.x;
     const int chain_waves = (NG + 63) / 64;
@@ -1581,6 +1574,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_si_sweep(Slab S, StepIO io, int
             const int s0 = c * C;
             const int ns = min(C, J - s0);
             double *ein = S.si_ein + ((size_t)s0 * NG + tid) * 2;
+#pragma unroll 4
             for (int sl = 0; sl < ns; ++sl) {
                 const double *v = src + (size_t)sl * per_step;
                 ein[(size_t)sl * NG * 2 + 0] = e0;
@@ -1595,6 +1589,44 @@ __global__ __launch_bounds__(kSweepBlock) void k_si_sweep(Slab S, StepIO io, int
     }
 }
 
+// One (cell, group, corner/level) entry of the flux pass: the iterate's
+// corner values from the base and the recorded incident edges, their
+// scalar flux (ascending m); returns its squared change.
+__device__ inline double si_flux_elem(const Slab &S, size_t t, int cur) {
+    const int u = t & 3;
+    const int N = S.N, G = S.G, NG = N * G;
+    const size_t jg = t >> 2;
+    const int g = (unsigned)jg % (unsigned)G, j = (unsigned)jg / (unsigned)G;
+    double *p = S.psi[cur ^ 1] + jg * N * 4 + u;
+    const double *rs = S.si_resp + jg * N * 8 + u;
+    double f = 0.0;
+#pragma unroll 4
+    for (int m = 0; m < N; ++m) {
+        const int step = S.mu[m] > 0.0 ? j : S.J - 1 - j;
+        const double *ei = S.si_ein + ((size_t)step * NG + g * N + m) * 2;
+        const double x = p[m * 4] + rs[m * 8] * ei[0] + rs[m * 8 + 4] * ei[1];
+        p[m * 4] = x;
+        f += S.w[m] * x;
+    }
+    const double f0 = S.phi[cur][t];
+    S.phi[cur ^ 1][t] = f;
+    return (f - f0) * (f - f0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_si_pre(Slab S) {
+    const Ctl *c = S.ctl;
+    if (c->done) return;
+    const int cur = (c->base + c->iter) & 1;
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < (size_t)S.J * S.G * S.N) si_pre_row(S, t, cur);
+}
+
+__global__ __launch_bounds__(kSweepBlock) void k_si_sweep(Slab S, StepIO io, int C) {
+    extern __shared__ __align__(16) double s_ring[];
+    if (S.ctl->done) return;
+    si_sweep_body(S, io, C, s_ring);
+}
+
 // phi of the sweep, its change, and the decision (last block to finish).
 __global__ __launch_bounds__(kBlock) void k_si_flux(Slab S) {
     __shared__ double s_tmp[kBlock / 64 + 1];
@@ -1603,27 +1635,7 @@ __global__ __launch_bounds__(kBlock) void k_si_flux(Slab S) {
     if (c->done) return;
     const int cur = (c->base + c->iter) & 1;
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    const size_t total = (size_t)S.J * S.G * 4;
-    double dsq = 0.0;
-    if (t < total) {
-        const int u = t & 3;
-        const int N = S.N, G = S.G, NG = N * G;
-        const size_t jg = t >> 2;
-        const int g = jg % G, j = jg / G;
-        double *p = S.psi[cur ^ 1] + jg * N * 4 + u;
-        const double *rs = S.si_resp + jg * N * 8 + u;
-        double f = 0.0;
-        for (int m = 0; m < N; ++m) {
-            const int step = S.mu[m] > 0.0 ? j : S.J - 1 - j;
-            const double *ei = S.si_ein + ((size_t)step * NG + g * N + m) * 2;
-            const double x = p[m * 4] + rs[m * 8] * ei[0] + rs[m * 8 + 4] * ei[1];
-            p[m * 4] = x;
-            f += S.w[m] * x;
-        }
-        const double f0 = S.phi[cur][t];
-        S.phi[cur ^ 1][t] = f;
-        dsq = (f - f0) * (f - f0);
-    }
+    const double dsq = t < (size_t)S.J * S.G * 4 ? si_flux_elem(S, t, cur) : 0.0;
     const double part = block_sum(dsq, s_tmp);
     if (threadIdx.x == 0) {
         S.partials[blockIdx.x] = part;
@@ -1640,6 +1652,66 @@ __global__ __launch_bounds__(kBlock) void k_si_flux(Slab S) {
     if (threadIdx.x == 0) {
         c->bar_count = 0;
         decide(S, sqrt(tot));
+    }
+}
+
+// The whole SI iteration loop of a step in one persistent launch: per
+// iteration the pre pass (grid-stride), a barrier, the chain sweep by
+// workgroup 0, a barrier, the flux pass and the norm, a barrier carrying the
+// norm; every workgroup then applies the stopping rule to the same total.
+// MULTI = false: one workgroup, workgroup barriers.  MULTI = true: grid
+// barriers whose agent-scope release/acquire make each phase's global
+// writes visible to every workgroup (grid_sync_sum).
+template <bool MULTI>
+__global__ __launch_bounds__(kSweepBlock) void k_si_loop(Slab S, StepIO io, int C) {
+    extern __shared__ __align__(16) double s_ring[];
+    __shared__ double s_tmp[kSweepBlock / 64 + 1];
+    __shared__ int s_flag[4];
+    const unsigned wg = blockIdx.x, nwg = gridDim.x;
+    const int base = S.ctl->base;
+    const size_t rows = (size_t)S.J * S.G * S.N, elems = (size_t)S.J * S.G * 4;
+    const size_t stride = (size_t)nwg * kSweepBlock, t0 = (size_t)wg * kSweepBlock + threadIdx.x;
+    double e_prev = __builtin_nan("");
+    int round = 0;
+    // a barrier between phases; the sum of the workgroups' v (valid in thread 0) in *total
+    auto barrier = [&](double v, double *total) -> bool {
+        if constexpr (MULTI) {
+            return grid_sync_sum<kSweepBlock>(S, wg, nwg, round++, v, s_flag, s_tmp, total);
+        } else {
+            __syncthreads();
+            if (threadIdx.x == 0) s_tmp[kSweepBlock / 64] = v;
+            __syncthreads();
+            *total = s_tmp[kSweepBlock / 64];
+            return true;
+        }
+    };
+    for (int l = 0;; ++l) {
+        const int cur = (base + l) & 1;
+        for (size_t t = t0; t < rows; t += stride) si_pre_row(S, t, cur);
+        double unused = 0.0;
+        if (!barrier(0.0, &unused)) return;
+        if (wg == 0) si_sweep_body(S, io, C, s_ring);
+        if (!barrier(0.0, &unused)) return;
+        double dsq = 0.0;
+        for (size_t t = t0; t < elems; t += stride) dsq += si_flux_elem(S, t, cur);
+        const double part = block_sum_t<kSweepBlock>(dsq, s_tmp);   // valid in thread 0
+        double tot = 0.0;
+        if (!barrier(part, &tot)) return;
+        const int iters = l + 1;
+        const double e = sqrt(tot);
+        int status = OK;
+        const int done = stop_rule(S, iters, e, e_prev, &status);
+        if (wg == 0 && threadIdx.x == 0) {
+            Ctl *c = S.ctl;
+            c->iter = iters;
+            c->e_last = e;
+            c->rho = iters >= 2 ? e / e_prev : __builtin_nan("");
+            c->e_prev = e;
+            c->status = status;
+            c->done = done;
+        }
+        e_prev = e;
+        if (done) return;
     }
 }
 
@@ -1972,6 +2044,26 @@ hipError_t launch_si_iteration(const Slab &S, const StepIO &io, hipStream_t st) 
     return hipGetLastError();
 }
 
-size_t si_flux_blocks(const Slab &S) { return ((size_t)S.J * S.G * 4 + kBlock - 1) / kBlock; }
+// The persistent SI loop: its dynamic LDS (the sweep ring) and how many of
+// its 1024-thread workgroups fit on one CU (0: not launchable).
+static size_t si_loop_lds(const Slab &S) { return (size_t)2 * si_chunk(S) * S.N * S.G * 6 * 8; }
+int si_loop_occupancy(const Slab &S, bool multi) {
+    const size_t dyn = si_loop_lds(S);
+    const void *f = multi ? (const void *)&k_si_loop<true> : (const void *)&k_si_loop<false>;
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess) return 0;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, kSweepBlock, dyn) != hipSuccess) return 0;
+    return occ;
+}
+hipError_t launch_si_loop(const Slab &S, const StepIO &io, int nwg, hipStream_t st) {
+    const size_t dyn = si_loop_lds(S);
+    const bool multi = nwg > 1;
+    const void *f = multi ? (const void *)&k_si_loop<true> : (const void *)&k_si_loop<false>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+    if (multi) hipLaunchKernelGGL(k_si_loop<true>, dim3(nwg), dim3(kSweepBlock), dyn, st, S, io, si_chunk(S));
+    else hipLaunchKernelGGL(k_si_loop<false>, dim3(1), dim3(kSweepBlock), dyn, st, S, io, si_chunk(S));
+    return hipGetLastError();
+}
 
 }  // namespace oci

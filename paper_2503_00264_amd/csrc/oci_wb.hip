@@ -230,11 +230,8 @@ __device__ inline bool wb_decide(const Slab &S, int wg, int l, double tot, doubl
     const int iters = l + 1;
     const double e = sqrt(tot);
     const double rho = iters >= 2 ? e / e_prev : __builtin_nan("");
-    int done = 0, status = OK;
-    if (!isfinite(e)) { done = 1; status = NONFINITE; }
-    else if (S.fixed_iters > 0) done = iters >= S.fixed_iters;
-    else if (iters >= 2 && (e == 0.0 || e < S.tol * (1.0 - e / e_prev))) done = 1;
-    else if (iters >= S.max_iters) { done = 1; status = NOT_CONVERGED; }
+    int status = OK;
+    const int done = stop_rule(S, iters, e, e_prev, &status);
     e_prev = e;
     if (S.hist && iters <= S.hist_cap && wg == 0 && threadIdx.x == 0) S.hist[iters - 1] = e;
     if (done && wg == 0 && threadIdx.x == 0) {

@@ -87,6 +87,38 @@ def test_oci_fp64_lockstep(name):
     assert rel(got, want) <= 1e-12
 
 
+@pytest.mark.parametrize("name", ["homogeneous64_n32", "regions512_n64", "multigroup192_n128", "single_cell",
+                                  "rosa_S8_dt10"])
+def test_si_loop_layouts_agree(name, monkeypatch):
+    """SI's iteration loop as the host-driven launch sequence, as one
+    persistent launch on one workgroup and on several: the same iterates bit
+    for bit (the passes do the same arithmetic in the same order; only the
+    norm's summation order differs), the same iteration counts, converged and
+    lock-step against the oracle."""
+    p, steps = CASES[name]
+    _announce(name, p, "si: launches / one / many")
+    want = oracle.Oracle(p).run("si", steps=steps, fixed_iters=5)["phi"]
+    ref = oracle.Oracle(p).run("si", steps=steps, tol=1e-14)["phi"]
+    outs = []
+    for mode in ("launches", "one", "many"):
+        monkeypatch.setenv("OCI_SI_MODE", mode)
+        s = B.Solver(p, precision=B.OCI_FP64, fixed_iters=5)
+        got, infos = s.run(steps=steps, method="si")
+        s.close()
+        assert all(i["iterations"] == 5 and i["status"] == 0 for i in infos), (mode, infos)
+        assert rel(got, want) <= 1e-12, mode
+        s = B.Solver(p, precision=B.OCI_FP64, tol=1e-12)
+        conv, cinfo = s.run(steps=steps, method="si")
+        s.close()
+        assert all(i["status"] == 0 for i in cinfo), (mode, cinfo)
+        assert rel(conv, ref) <= 1e-10, mode
+        outs.append((got, conv, [i["iterations"] for i in cinfo]))
+    for got, conv, its in outs[1:]:
+        assert np.array_equal(got, outs[0][0])
+        assert its == outs[0][2]
+        assert rel(conv, outs[0][1]) <= 1e-14
+
+
 @pytest.mark.parametrize("name", ["homogeneous64_n32", "regions512_n64", "multigroup192_n128",
                                   "G3_n48", "single_cell", "N2_J5", "rosa_S8_dt10", "rosa_S16_dt0.1"])
 def test_si_fp64_lockstep(name):
