@@ -68,6 +68,23 @@ __device__ inline void corner_inverse(double mu, double tau, double a, cplx &e2,
     e3 = cmul({d, h}, r);
 }
 
+// corner_inverse with the reciprocal from the hardware estimate refined by
+// two Newton steps (r <- r (2 - q r)) instead of the correctly rounded
+// division: a relative error of a few units in the last place, no
+// division sequence (the staged body recomputes it every iteration).
+__device__ inline void corner_inverse_nr(double mu, double tau, double a, cplx &e2, cplx &e3) {
+    const double d = 0.5 * (fabs(mu) + tau);
+    const double h = 0.5 * mu;
+    const cplx delta = {d * (d + a) - h * h + 0.5 * a * a, h * (2.0 * d + a)};
+    const double q = cabs2(delta);
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(r, fma(-q, r, 1.0), r);
+    r = fma(r, fma(-q, r, 1.0), r);
+    const cplx inv = {delta.re * r, -delta.im * r};
+    e2 = cscale(0.5 * a, inv);
+    e3 = cmul({d, h}, inv);
+}
+
 // (X_k, X_h) = L_c^-1 (B_k, B_h) in the complex form.
 __device__ inline void corner_apply(cplx e2, cplx e3, cplx bk, cplx bh, cplx &xk, cplx &xh) {
     const cplx r = cmul(e2, bk);
@@ -613,6 +630,15 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
     for (int m = tid; m < N; m += BS) { s_mu[m] = S.mu[m]; s_w[m] = S.w[m]; }
     if (wg == 0 && tid == 0) S.ctl->t_begin = wall_clock64();
     __syncthreads();
+    // this lane's node, weight and 1/(v dt) of each pair, fixed for the launch
+    double mu_q[Q], w_q[Q], ivdt_q[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = li + q * lc < NG ? li + q * lc : 0;
+        mu_q[q] = s_mu[i & (N - 1)];
+        w_q[q] = li + q * lc < NG ? s_w[i & (N - 1)] : 0.0;
+        ivdt_q[q] = s_ivdt[i >> lgN];
+    }
     const size_t ehalf = (size_t)J * NG * 2;
     const bool rb = S.ordering == 1;
     const int nhalf = rb ? 2 : 1;
@@ -730,7 +756,7 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                     for (int q = 0; q < Q; ++q) {
                         const bool act = cell && li + q * lc < NG;
                         const int g = pair_of(q) >> lgN, m = pair_of(q) & (N - 1);
-                        const double mu = s_mu[m];
+                        const double mu = mu_q[q];
                         const double2 pp = Pv[q * 64 + lane];
                         double ek, eh;
                         if (!from_iterate) {
@@ -749,7 +775,7 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                             ek = eh = 0.0;
                             if (act && inc) load2_now(inc + (size_t)g * nh + mi, inc + ((size_t)G + g) * nh + mi, ek, eh);
                         }
-                        const double ivdt = s_ivdt[g];
+                        const double ivdt = ivdt_q[q];
                         const double ht = 0.5 * dx * ivdt;
                         double b0 = ht * pp.x, b1 = ht * pp.y, b2 = 0.0, b3 = 0.0;
                         if (io.q) {
@@ -767,9 +793,9 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                             b1 -= mu * ek;
                             b3 -= mu * eh;
                         }
-                        corner_inverse(mu, dx * Cd[c_st + cw * G + g], dx * ivdt, e2[q], e3[q]);
+                        corner_inverse_nr(mu, dx * Cd[c_st + cw * G + g], dx * ivdt, e2[q], e3[q]);
                         corner_apply(e2[q], e3[q], cplx{b0, -b1}, cplx{b2, -b3}, z[q][0], z[q][1]);
-                        const double w = act ? s_w[m] : 0.0;
+                        const double w = cell ? w_q[q] : 0.0;
                         mom[q][0] = cscale(w, z[q][0]);
                         mom[q][1] = cscale(w, z[q][1]);
                     }
