@@ -486,19 +486,25 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
 // system (global_load_lds: the data lands in LDS without passing through
 // registers), one tile ahead of the arithmetic, so a wave keeps a tile's worth
 // of loads in flight while it computes the previous tile.  Per tile t a wave
-//   waits for its staged inputs of t (psi_{k-1/2}, upstream corners, the
-//   cells' sources, scalar flux, cross sections and widths);
-//   forms b and z = L_c^-1 b; sums the moments over m by a butterfly across
-//   the N lanes of each group; then issues the staging of t + 1;
-//   waits for the rows of (I - W C)^-1 of t (issued one tile earlier), forms
-//   t = (I - W C)^-1 V^T z and C t = (dx/4) (Sigma_s (x) I) t; stores the new
-//   scalar flux; then issues the rows of t + 1;
+//   waits for the staged data of t: the rows of (I - W C)^-1 of its cells,
+//   then psi_{k-1/2}, upstream corners, the cells' sources, scalar flux,
+//   cross sections and widths;
+//   forms b and z = L_c^-1 b; then issues the staging of t + 1 (the rows into
+//   the other of two row buffers, then the inputs);
+//   sums the moments over m by a butterfly across the N lanes of each group;
+//   forms t = (I - W C)^-1 V^T z and C t = (dx/4) (Sigma_s (x) I) t; stores
+//   the new scalar flux;
 //   forms x = z + L_c^-1 (C t)_g and stores the outgoing corners.
 // Vector memory operations complete in issue order, so "the loads of t have
 // landed" is "at most k operations are outstanding", k the number issued
-// after them; every staging load and every store is issued by all 64 lanes
-// (addresses of idle lanes clamped into the slab, stores of idle lanes sent
-// past the end of a buffer resource, which drops them), so k is known.
+// after them: the previous tile's stores, one for the scalar flux and Q for
+// the corners (2Q and none on the final pass, which is more).  Every staging
+// load and every store is issued by all 64 lanes (addresses of idle lanes
+// clamped into the slab, stores of idle lanes sent past the end of a buffer
+// resource, which drops them), and after the staging of a wave's first tile
+// come 1 + Q one-dword loads into a slot that nothing reads, so one wait with
+// a fixed count serves every tile.  (A store that every lane drops is never
+// counted on: it need not wait for the memory system to retire.)
 // Shapes: N a power of two in [8, 64], G in {1, 2, 4}, at most two pairs per
 // lane, a wave's rows of (I - W C)^-1 within 2 KiB and its per-cell data
 // within 1 KiB (wb_staged_shape); other shapes take the direct body above.
@@ -522,39 +528,33 @@ struct WbStage {
     static constexpr int kP = 0;               // psi_{k-1/2} of the lanes' pairs: [Q][64] x 16 B
     static constexpr int kE = kP + Q * 1024;   // upstream corners: [Q][64] x 16 B, or [Q][4][64] dwords
     static constexpr int kC = kE + Q * 1024;   // per-cell data: 256 dwords
-    static constexpr int kM = kC + 1024;       // rows of (I - W C)^-1: 128 complex words
-    static constexpr int kB = kM + 2048;       // moments V^T z: 16 complex words
+    static constexpr int kM = kC + 1024;       // rows of (I - W C)^-1: [2][128] complex words
+    static constexpr int kB = kM + 4096;       // moments V^T z: 16 complex words
     static constexpr int kT = kB + 256;        // t, then C t: 32 complex words
-    static constexpr int kBytes = kT + 512;
+    static constexpr int kD = kT + 512;        // target of the count-keeping loads: 64 dwords
+    static constexpr int kBytes = kD + 256;
 };
 
-// s_waitcnt vmcnt(k) for a wave-uniform k; k above 31 waits for 31 (more
-// than asked, never less).
-#define OCI_VMW(n) \
-    case n: asm volatile("s_waitcnt vmcnt(" #n ")" ::: "memory"); break;
-__device__ inline void vm_wait(int k) {
-    switch (k < 0 ? 0 : (k > 31 ? 31 : k)) {
-        OCI_VMW(0) OCI_VMW(1) OCI_VMW(2) OCI_VMW(3) OCI_VMW(4) OCI_VMW(5) OCI_VMW(6) OCI_VMW(7)
-        OCI_VMW(8) OCI_VMW(9) OCI_VMW(10) OCI_VMW(11) OCI_VMW(12) OCI_VMW(13) OCI_VMW(14) OCI_VMW(15)
-        OCI_VMW(16) OCI_VMW(17) OCI_VMW(18) OCI_VMW(19) OCI_VMW(20) OCI_VMW(21) OCI_VMW(22) OCI_VMW(23)
-        OCI_VMW(24) OCI_VMW(25) OCI_VMW(26) OCI_VMW(27) OCI_VMW(28) OCI_VMW(29) OCI_VMW(30) OCI_VMW(31)
-        default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    }
+// s_waitcnt vmcnt(K): at most K of the wave's vector memory operations
+// remain outstanding.
+template <int K>
+__device__ inline void vm_wait() {
+    static_assert(K >= 0 && K < 64, "vmcnt is a 6-bit count");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(K) : "memory");
 }
-#undef OCI_VMW
 
 // The wave's LDS reads issued so far have returned (before the memory system
 // may overwrite what they read); also a compiler barrier for memory accesses.
 __device__ inline void lds_reads_done() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
-// 16 bytes (lane i's at lds + 16 i) or 4 bytes (at lds + 4 i) from each
-// lane's address into LDS; SC1: agent-coherent, as ld_coherent.  Written as
-// inline assembly so that the compiler, which cannot tell the staging areas
-// apart, does not wait for every staging load before each LDS read: the body
-// orders them itself (vm_wait).  M0 (the LDS base) is saved and restored.
+// 16 bytes (lane i's at LDS byte address lds + 16 i) or 4 bytes (at lds +
+// 4 i) from each lane's address into LDS; lds is wave-uniform; SC1:
+// agent-coherent, as ld_coherent.  Written as inline assembly so that the
+// compiler, which cannot tell the staging areas apart, does not wait for every
+// staging load before each LDS read: the body orders them itself (vm_wait).
+// M0 (the LDS base) is saved and restored.
 template <bool SC1>
-__device__ inline void stage16(const void *src, unsigned char *lds) {
-    const unsigned base = __builtin_amdgcn_readfirstlane((unsigned)(size_t)(lds_void *)lds);
+__device__ inline void stage16(const void *src, unsigned base) {
     unsigned saved;
     if (SC1)
         asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off sc1\n\t"
@@ -565,8 +565,7 @@ __device__ inline void stage16(const void *src, unsigned char *lds) {
                      "s_mov_b32 m0, %0"
                      : "=&s"(saved) : "v"(src), "s"(base) : "memory");
 }
-__device__ inline void stage4(const void *src, unsigned char *lds) {
-    const unsigned base = __builtin_amdgcn_readfirstlane((unsigned)(size_t)(lds_void *)lds);
+__device__ inline void stage4(const void *src, unsigned base) {
     unsigned saved;
     asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %1, off\n\t"
                  "s_mov_b32 m0, %0"
@@ -594,6 +593,81 @@ __device__ inline void store16(__amdgpu_buffer_rsrc_t r, unsigned off, double a,
 
 __device__ inline int ilog2(int v) { return 31 - __builtin_clz(v); }
 
+// Cross-lane sums without LDS.  Lane partners across bit B of the lane index:
+// B = 5 and 4 by the permlane swaps (lanes i and i ^ 32, i and i ^ 16), B = 3
+// and 2 by the DPP row mirrors (i and i ^ 15, i and i ^ 7 within rows of 16
+// lanes), B = 1 and 0 by DPP quad permutations (i ^ 2, i ^ 1).  Every lane of
+// the wave takes part.
+template <int B>
+struct LaneXor {
+    static constexpr int kDpp = B == 3 ? 0x140 : B == 2 ? 0x141 : B == 1 ? 0x4E : 0xB1;
+};
+template <int B>
+__device__ inline double dpp_partner(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, LaneXor<B>::kDpp, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), LaneXor<B>::kDpp, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// Permlane swap of (a, b): lanes whose bit B is 0 get a and the partner's a,
+// the others b and the partner's b; returned as (first, second) summed.
+template <int B>
+__device__ inline double swap_sum(double a, double b) {
+    const long long va = __double_as_longlong(a), vb = __double_as_longlong(b);
+    unsigned lo0, lo1, hi0, hi1;
+    if constexpr (B == 5) {
+        const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)va, (unsigned)vb, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(va >> 32), (unsigned)(vb >> 32), false, false);
+        lo0 = lo[0]; lo1 = lo[1]; hi0 = hi[0]; hi1 = hi[1];
+    } else {
+        const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)va, (unsigned)vb, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(va >> 32), (unsigned)(vb >> 32), false, false);
+        lo0 = lo[0]; lo1 = lo[1]; hi0 = hi[0]; hi1 = hi[1];
+    }
+    return __hiloint2double((int)hi0, (int)lo0) + __hiloint2double((int)hi1, (int)lo1);
+}
+// One reduce-scatter level across bit B: a lane whose bit B is 0 keeps a plus
+// the partner's a, the other keeps b plus the partner's b.
+template <int B>
+__device__ inline double rs_level(double a, double b, bool bit) {
+    if constexpr (B >= 4) {
+        return swap_sum<B>(a, b);
+    } else {
+        const double send = bit ? a : b, keep = bit ? b : a;
+        return keep + dpp_partner<B>(send);
+    }
+}
+// One full level across bit B: x plus the partner's x.
+template <int B>
+__device__ inline double full_level(double x) {
+    if constexpr (B >= 4) return swap_sum<B>(x, x);
+    else return x + dpp_partner<B>(x);
+}
+// Sums over each group of 2^LGN consecutive lanes of the two complex values
+// m[0], m[1] of every lane.  Two reduce-scatter levels over the group's two
+// highest lane bits, then full levels over the rest: the lane whose bits
+// LGN-1, LGN-2 are (h, p) holds part p (0: real, 1: imaginary) of the group
+// sum of m[h].
+template <int LGN>
+__device__ inline double group_sum2c(const cplx m[2], int lane) {
+    const bool b1 = (lane >> (LGN - 1)) & 1, b2 = (lane >> (LGN - 2)) & 1;
+    const double re = rs_level<LGN - 1>(m[0].re, m[1].re, b1);
+    const double im = rs_level<LGN - 1>(m[0].im, m[1].im, b1);
+    double x = rs_level<LGN - 2>(re, im, b2);
+    if constexpr (LGN >= 6) x = full_level<3>(x);
+    if constexpr (LGN >= 5) x = full_level<2>(x);
+    if constexpr (LGN >= 4) x = full_level<1>(x);
+    return full_level<0>(x);
+}
+__device__ inline double group_sum2c(const cplx m[2], int lane, int lgN) {
+    switch (lgN) {
+        case 3: return group_sum2c<3>(m, lane);
+        case 4: return group_sum2c<4>(m, lane);
+        case 5: return group_sum2c<5>(m, lane);
+        default: return group_sum2c<6>(m, lane);
+    }
+}
+
 template <int Q, int BS>
 __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab &S, const StepIO &io, int ntiles,
                                                                 int wg, unsigned nwg, unsigned char *lds,
@@ -608,6 +682,9 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
     const int cpt = W * cpw;
     const int lgN = ilog2(N), lgG = ilog2(G);
     unsigned char *A = lds + (size_t)wave * WbStage<Q>::kBytes;
+    // the wave's area as an LDS byte address (wave-uniform) for the staging loads
+    const unsigned a_lds = __builtin_amdgcn_readfirstlane((unsigned)(size_t)(lds_void *)A);
+    const int lglc = ilog2(lc);
     const double2 *Pv = reinterpret_cast<const double2 *>(A + WbStage<Q>::kP);
     const double2 *Ev = reinterpret_cast<const double2 *>(A + WbStage<Q>::kE);
     const unsigned *Ed = reinterpret_cast<const unsigned *>(A + WbStage<Q>::kE);
@@ -618,11 +695,11 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
     // per-cell data, one 64-dword staging load each, in doubles: q
     // [cpw][G][4] at 0, phi [cpw][G][4] at 32, Sigma_s [cpw][G][G] at 64,
     // Sigma_t [cpw][G] at 96, dx [cpw] at 112 (cpw G <= 8, cpw <= 8)
-    constexpr int c_phi = 32, c_ss = 64, c_st = 96, c_dx = 112, nC = 4;
+    constexpr int c_phi = 32, c_ss = 64, c_st = 96, c_dx = 112;
     // this lane's pair q (any pair of the cell for padding lanes)
     auto pair_of = [&](int q) { return li + q * lc < NG ? li + q * lc : 0; };
     const int m_words = cpw * 4 * G * G;       // 16-byte words of the wave's rows
-    const int nM = (m_words + 63) >> 6;
+    const int nM = (m_words + 63) >> 6;        // 1 or 2
     const int lgM = 2 + 2 * lgG;               // log2(4 G^2)
     const int tile0 = (int)(((long)ntiles * wg) / nwg);
     const int tile1 = (int)(((long)ntiles * (wg + 1)) / nwg);
@@ -659,14 +736,9 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
         bool fin = false;
         for (int pass = 0; pass < 2; ++pass) {
             if (pass == 1 && !fin) break;
-            // stores per tile, in issue order: the scalar flux (pass 0), then
-            // the corners (pass 0: one per pair; pass 1: the whole iterate,
-            // two per pair)
-            const int s_phi = pass == 0 ? 1 : 0, s_x = pass == 0 ? Q : 2 * Q;
             for (int half = 0; half < nhalf; ++half) {
                 const bool from_iterate = l == 0 && half == 0;
                 const double *edges = half == 1 ? e_out : e_in;
-                const int nPEC = Q + (from_iterate ? 4 * Q : Q) + nC;
                 auto cell_of = [&](int tile, int c) {
                     const int cc = tile * cpt + wave * cpw + c;
                     return rb ? 2 * cc + half : cc;
@@ -677,14 +749,14 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                     // live across the tile loop (register pressure)
                     int ln = lane;
                     asm volatile("" : "+v"(ln));
-                    const int lcw = ln / lc, lli = ln % lc;
+                    const int lcw = ln >> lglc, lli = ln & (lc - 1);
                     const int jc = cell_of(tile, lcw);
                     const int jj = jc < J ? jc : J - 1;
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
                         const int i = lli + q * lc < NG ? lli + q * lc : 0;
                         const int row = jj * NG + i;   // (j, g, m) with i = g N + m; J NG < 2^26
-                        stage16<false>(S.psi_prev + (size_t)row * 2, A + WbStage<Q>::kP + q * 1024);
+                        stage16<false>(S.psi_prev + (size_t)row * 2, a_lds + WbStage<Q>::kP + q * 1024);
                         const bool right = (i & (N - 1)) >= nh;
                         int up = row;   // no upstream cell: any address in the slab
                         if (right) {
@@ -695,10 +767,10 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                             else if (S.periodic) up = row - (J - 1) * NG;
                         }
                         if (!from_iterate) {
-                            stage16<true>(edges + (size_t)up * 2, A + WbStage<Q>::kE + q * 1024);
+                            stage16<true>(edges + (size_t)up * 2, a_lds + WbStage<Q>::kE + q * 1024);
                         } else {   // the corner of the first iterate: dwords of psi[up][c], psi[up][c + 2]
                             const unsigned *pc = reinterpret_cast<const unsigned *>(psi_in + (size_t)up * 4 + (right ? 1 : 0));
-                            unsigned char *e = A + WbStage<Q>::kE + q * 1024;
+                            const unsigned e = a_lds + WbStage<Q>::kE + q * 1024;
                             stage4(pc, e);
                             stage4(pc + 1, e + 256);
                             stage4(pc + 4, e + 512);
@@ -709,7 +781,7 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                         const int jx = cell_of(tile, c);
                         return jx < J ? jx : J - 1;
                     };
-                    unsigned char *C = A + WbStage<Q>::kC;
+                    const unsigned C = a_lds + WbStage<Q>::kC;
                     // this lane's dword of each per-cell load: (cell of the
                     // wave, dword in the cell's record)
                     const int cq = ln >> (3 + lgG), oq = ln & (8 * G - 1);
@@ -725,7 +797,8 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                                              : reinterpret_cast<const unsigned *>(S.sigma_t) + jt * 2 * G + ot;
                     stage4(pt, C + 768);
                 };
-                // stage the rows of (I - W C)^-1 of a tile's cells
+                // stage the rows of (I - W C)^-1 of a tile's cells, into row
+                // buffer tile & 1
                 auto stage_rows = [&](int tile) {
                     for (int k = 0; k < nM; ++k) {
                         const int d = k * 64 + lane;
@@ -734,21 +807,23 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                             const int j = cell_of(tile, d >> lgM);
                             src = Wb + (size_t)(j < J ? j : J - 1) * 2 * R * R + (d & ((1 << lgM) - 1));
                         }
-                        stage16<false>(src, A + WbStage<Q>::kM + k * 1024);
+                        stage16<false>(src, a_lds + WbStage<Q>::kM + (tile & 1) * 2048 + k * 1024);
                     }
                 };
                 if (tile0 < tile1) {
-                    stage_inputs(tile0);
                     stage_rows(tile0);
+                    stage_inputs(tile0);
+#pragma unroll
+                    for (int k = 0; k < 1 + Q; ++k) stage4(S.dx, a_lds + WbStage<Q>::kD);
                 }
                 for (int tile = tile0; tile < tile1; ++tile) {
-                    const bool first = tile == tile0, more = tile + 1 < tile1;
+                    const bool more = tile + 1 < tile1;
                     const int j = cell_of(tile, cw);
                     const bool cell = j < J;
-                    // (1) the staged inputs of this tile have landed: after them
-                    //     came the rows (nM) and, but on the first tile, the
-                    //     previous tile's stores
-                    vm_wait(first ? nM : s_phi + nM + s_x);
+                    // (1) the staged rows and inputs of this tile have landed:
+                    //     after them came at least 1 + Q operations (the
+                    //     previous tile's stores, or the count-keeping loads)
+                    vm_wait<1 + Q>();
                     const double dx = Cd[c_dx + cw];
                     cplx z[Q][2], e2[Q], e3[Q];
                     cplx mom[Q][2];
@@ -811,32 +886,29 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                             if (gp < G) ssr[gp] = ss[gp];
                     }
                     lds_reads_done();
-                    // (2) the staged inputs are consumed: stage the next tile's
-                    if (more) stage_inputs(tile + 1);
-                    // (3) moments: butterfly over the N lanes of each group
-#pragma unroll
-                    for (int q = 0; q < Q; ++q)
-                        for (int off = N >> 1; off > 0; off >>= 1)
-#pragma unroll
-                            for (int h = 0; h < 2; ++h) {
-                                mom[q][h].re += __shfl_xor(mom[q][h].re, off, 64);
-                                mom[q][h].im += __shfl_xor(mom[q][h].im, off, 64);
-                            }
+                    // (2) the staged inputs are consumed, and the rows of the
+                    //     previous tile: stage the next tile's
+                    if (more) {
+                        stage_rows(tile + 1);
+                        stage_inputs(tile + 1);
+                    }
+                    // (3) moments: sums over the N lanes of each group across
+                    //     lanes (a group's lanes are N consecutive lanes of the
+                    //     wave, so lane bits below log2 N are bits of m); four
+                    //     lanes of a group hold one real part each
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        const int i = li + q * lc;
-                        if (cell && i < NG && (i & (N - 1)) == 0) {
-                            const int g = i >> lgN;
-                            Zcell[2 * g] = mom[q][0];
-                            Zcell[2 * g + 1] = mom[q][1];
+                        const double v = group_sum2c(mom[q], lane, lgN);
+                        const int i = li + q * lc, m = i & (N - 1);
+                        if (cell && i < NG && (m & ((N >> 2) - 1)) == 0) {
+                            const int g = i >> lgN, h = (m >> (lgN - 1)) & 1, part = (m >> (lgN - 2)) & 1;
+                            reinterpret_cast<double *>(Zcell)[(2 * g + h) * 2 + part] = v;
                         }
                     }
                     wave_sync();
-                    // (4) t = (I - W C)^-1 V^T z from the staged rows: after
-                    //     them came the previous tile's corner stores (not on
-                    //     the first tile) and the next tile's staging
-                    vm_wait((first ? 0 : s_x) + (more ? nPEC : 0));
-                    if (cell && li < R) Tcell[li] = row_dot(Mv + ((size_t)cw << lgM) + (size_t)li * R, Zcell, R);
+                    // (4) t = (I - W C)^-1 V^T z from the staged rows
+                    if (cell && li < R)
+                        Tcell[li] = row_dot(Mv + ((size_t)(tile & 1) << 7) + ((size_t)cw << lgM) + (size_t)li * R, Zcell, R);
                     wave_sync();
                     // (5) C t = (dx/4) sum_g' Sigma_s[g][g'] t_g' on each level;
                     //     the scalar flux is t itself
@@ -858,11 +930,8 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                         }
                     }
                     if (pass == 0) store16<0>(r_phi, phi_off, n0, n1);
-                    lds_reads_done();
-                    // (6) the rows are consumed: stage the next tile's
-                    if (more) stage_rows(tile + 1);
                     wave_sync();
-                    // (7) x = z + L_c^-1 (C t)_g; the outgoing corners (the
+                    // (6) x = z + L_c^-1 (C t)_g; the outgoing corners (the
                     //     whole iterate after a stop)
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
