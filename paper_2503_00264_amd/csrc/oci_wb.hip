@@ -593,6 +593,22 @@ __device__ inline void store16(__amdgpu_buffer_rsrc_t r, unsigned off, double a,
 
 __device__ inline int ilog2(int v) { return 31 - __builtin_clz(v); }
 
+// sum_c row[c] v[c] over the R words of a row, every word loaded before the
+// first multiply-add (one LDS round trip)
+template <int R>
+__device__ inline cplx row_dot_r(const cplx *row, const cplx *v) {
+    cplx w[R], x[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        w[c] = row[c];
+        x[c] = v[c];
+    }
+    cplx acc{0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc = cadd(acc, cmul(w[c], x[c]));
+    return acc;
+}
+
 // Cross-lane sums without LDS.  Lane partners across bit B of the lane index:
 // B = 5 and 4 by the permlane swaps (lanes i and i ^ 32, i and i ^ 16), B = 3
 // and 2 by the DPP row mirrors (i and i ^ 15, i and i ^ 7 within rows of 16
@@ -722,6 +738,11 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
     double e_prev = __builtin_nan("");
     const int base = S.ctl->base;
     const cplx *Wb = reinterpret_cast<const cplx *>(S.wb);
+    // flags the tile loop tests, held in registers for the launch (a reload of
+    // a scalar field waits for every LDS read in flight)
+    int periodic = __builtin_amdgcn_readfirstlane(S.periodic);
+    int has_q = __builtin_amdgcn_readfirstlane(io.q != nullptr ? 1 : 0);
+    asm volatile("" : "+s"(periodic), "+s"(has_q));
     for (int l = 0;; ++l) {
         const int cur = (base + l) & 1;
         const double *psi_in = S.psi[cur];
@@ -761,10 +782,10 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                         int up = row;   // no upstream cell: any address in the slab
                         if (right) {
                             if (jj > 0) up = row - NG;
-                            else if (S.periodic) up = row + (J - 1) * NG;
+                            else if (periodic) up = row + (J - 1) * NG;
                         } else {
                             if (jj < J - 1) up = row + NG;
-                            else if (S.periodic) up = row - (J - 1) * NG;
+                            else if (periodic) up = row - (J - 1) * NG;
                         }
                         if (!from_iterate) {
                             stage16<true>(edges + (size_t)up * 2, a_lds + WbStage<Q>::kE + q * 1024);
@@ -824,66 +845,53 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                     //     after them came at least 1 + Q operations (the
                     //     previous tile's stores, or the count-keeping loads)
                     vm_wait<1 + Q>();
+                    // every LDS read of the tile's inputs, before any use
                     const double dx = Cd[c_dx + cw];
-                    cplx z[Q][2], e2[Q], e3[Q];
-                    cplx mom[Q][2];
+                    double2 pp[Q], ev[Q], qa[Q], qb[Q];
+                    double st[Q];
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        const bool act = cell && li + q * lc < NG;
-                        const int g = pair_of(q) >> lgN, m = pair_of(q) & (N - 1);
-                        const double mu = mu_q[q];
-                        const double2 pp = Pv[q * 64 + lane];
-                        double ek, eh;
+                        const int g = pair_of(q) >> lgN;
+                        pp[q] = Pv[q * 64 + lane];
                         if (!from_iterate) {
-                            const double2 ev = Ev[q * 64 + lane];
-                            ek = ev.x;
-                            eh = ev.y;
+                            ev[q] = Ev[q * 64 + lane];
                         } else {
                             const unsigned *e = Ed + q * 256 + lane;
-                            ek = __hiloint2double((int)e[64], (int)e[0]);
-                            eh = __hiloint2double((int)e[192], (int)e[128]);
+                            ev[q] = double2{__hiloint2double((int)e[64], (int)e[0]),
+                                            __hiloint2double((int)e[192], (int)e[128])};
                         }
-                        const bool up_in = m >= nh ? (j > 0 || S.periodic) : (j < J - 1 || S.periodic);
-                        if (!up_in) {   // the slab's boundary: incident flux, or vacuum
-                            const double *inc = m >= nh ? io.inc_l : io.inc_r;
-                            const int mi = m >= nh ? m - nh : m;
-                            ek = eh = 0.0;
-                            if (act && inc) load2_now(inc + (size_t)g * nh + mi, inc + ((size_t)G + g) * nh + mi, ek, eh);
-                        }
-                        const double ivdt = ivdt_q[q];
-                        const double ht = 0.5 * dx * ivdt;
-                        double b0 = ht * pp.x, b1 = ht * pp.y, b2 = 0.0, b3 = 0.0;
-                        if (io.q) {
-                            const double *qq = Cd + (cw * G + g) * 4;
-                            const double q4 = 0.25 * dx;
-                            b0 += q4 * qq[0];
-                            b1 += q4 * qq[1];
-                            b2 = q4 * qq[2];
-                            b3 = q4 * qq[3];
-                        }
-                        if (m >= nh) {
-                            b0 += mu * ek;
-                            b2 += mu * eh;
-                        } else {
-                            b1 -= mu * ek;
-                            b3 -= mu * eh;
-                        }
-                        corner_inverse_nr(mu, dx * Cd[c_st + cw * G + g], dx * ivdt, e2[q], e3[q]);
-                        corner_apply(e2[q], e3[q], cplx{b0, -b1}, cplx{b2, -b3}, z[q][0], z[q][1]);
-                        const double w = cell ? w_q[q] : 0.0;
-                        mom[q][0] = cscale(w, z[q][0]);
-                        mom[q][1] = cscale(w, z[q][1]);
+                        const double2 *qq = reinterpret_cast<const double2 *>(Cd + (cw * G + g) * 4);
+                        qa[q] = qq[0];
+                        qb[q] = qq[1];
+                        st[q] = Cd[c_st + cw * G + g];
                     }
                     // the previous scalar flux of this lane's (g, level), for the
-                    // norm, and its row of Sigma_s, read before the restaging
-                    double2 fprev{0.0, 0.0};
-                    double ssr[4] = {0.0, 0.0, 0.0, 0.0};
-                    if (li < R) {
-                        if (pass == 0) fprev = *reinterpret_cast<const double2 *>(Cd + c_phi + cw * 4 * G + 2 * li);
-                        const double *ss = Cd + c_ss + (cw * G + (li >> 1)) * G;
+                    // norm, and its row of Sigma_s (lanes li < R; the others read
+                    // in-range words and drop them)
+                    const int lr = li < R ? li : 0;
+                    const double2 fp = *reinterpret_cast<const double2 *>(Cd + c_phi + cw * 4 * G + 2 * lr);
+                    const double *ss = Cd + c_ss + (cw * G + (lr >> 1)) * G;
+                    double ssr[4];
 #pragma unroll
-                        for (int gp = 0; gp < 4; ++gp)
-                            if (gp < G) ssr[gp] = ss[gp];
+                    for (int gp = 0; gp < 4; ++gp) {
+                        const double v = ss[gp < G ? gp : 0];
+                        ssr[gp] = li < R && gp < G ? v : 0.0;
+                    }
+                    const double2 fprev = li < R && pass == 0 ? fp : double2{0.0, 0.0};
+                    // the slab's boundary: the incident flux, or vacuum (before
+                    // the restaging, whose loads the wait here would include)
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const int g = pair_of(q) >> lgN, m = pair_of(q) & (N - 1);
+                        const bool up_in = m >= nh ? (j > 0 || periodic) : (j < J - 1 || periodic);
+                        if (!up_in) {
+                            const double *inc = m >= nh ? io.inc_l : io.inc_r;
+                            const int mi = m >= nh ? m - nh : m;
+                            double ek = 0.0, eh = 0.0;
+                            if (cell && li + q * lc < NG && inc)
+                                load2_now(inc + (size_t)g * nh + mi, inc + ((size_t)G + g) * nh + mi, ek, eh);
+                            ev[q] = double2{ek, eh};
+                        }
                     }
                     lds_reads_done();
                     // (2) the staged inputs are consumed, and the rows of the
@@ -891,6 +899,31 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                     if (more) {
                         stage_rows(tile + 1);
                         stage_inputs(tile + 1);
+                    }
+                    cplx z[Q][2], e2[Q], e3[Q];
+                    cplx mom[Q][2];
+                    const double q4 = has_q ? 0.25 * dx : 0.0;   // no source: the staged words are unused
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const int m = pair_of(q) & (N - 1);
+                        const double mu = mu_q[q];
+                        const double ek = ev[q].x, eh = ev[q].y;
+                        const double ivdt = ivdt_q[q];
+                        const double ht = 0.5 * dx * ivdt;
+                        double b0 = ht * pp[q].x + q4 * qa[q].x, b1 = ht * pp[q].y + q4 * qa[q].y;
+                        double b2 = q4 * qb[q].x, b3 = q4 * qb[q].y;
+                        if (m >= nh) {
+                            b0 += mu * ek;
+                            b2 += mu * eh;
+                        } else {
+                            b1 -= mu * ek;
+                            b3 -= mu * eh;
+                        }
+                        corner_inverse_nr(mu, dx * st[q], dx * ivdt, e2[q], e3[q]);
+                        corner_apply(e2[q], e3[q], cplx{b0, -b1}, cplx{b2, -b3}, z[q][0], z[q][1]);
+                        const double w = cell ? w_q[q] : 0.0;
+                        mom[q][0] = cscale(w, z[q][0]);
+                        mom[q][1] = cscale(w, z[q][1]);
                     }
                     // (3) moments: sums over the N lanes of each group across
                     //     lanes (a group's lanes are N consecutive lanes of the
@@ -907,8 +940,21 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                     }
                     wave_sync();
                     // (4) t = (I - W C)^-1 V^T z from the staged rows
-                    if (cell && li < R)
-                        Tcell[li] = row_dot(Mv + ((size_t)(tile & 1) << 7) + ((size_t)cw << lgM) + (size_t)li * R, Zcell, R);
+                    //     (a lane pair per row, each lane half of its words; the
+                    //     halves summed across the pair)
+                    {
+                        cplx tp{0.0, 0.0};
+                        if (cell && li < 2 * R) {
+                            const int hw = (li & 1) * G;   // R / 2 = G words per lane
+                            const cplx *row =
+                                Mv + ((size_t)(tile & 1) << 7) + ((size_t)cw << lgM) + (size_t)(li >> 1) * R + hw;
+                            tp = G == 4 ? row_dot_r<4>(row, Zcell + hw)
+                                        : G == 2 ? row_dot_r<2>(row, Zcell + hw) : row_dot_r<1>(row, Zcell + hw);
+                        }
+                        tp.re += dpp_partner<0>(tp.re);
+                        tp.im += dpp_partner<0>(tp.im);
+                        if (cell && li < 2 * R && (li & 1) == 0) Tcell[li >> 1] = tp;
+                    }
                     wave_sync();
                     // (5) C t = (dx/4) sum_g' Sigma_s[g][g'] t_g' on each level;
                     //     the scalar flux is t itself
@@ -918,8 +964,8 @@ __device__ __attribute__((always_inline)) inline void wb_body_staged(const Slab 
                         const int g = li >> 1, kk = li & 1;
                         cplx ct{0.0, 0.0};
 #pragma unroll
-                        for (int gp = 0; gp < 4; ++gp)
-                            if (gp < G) ct = cadd(ct, cscale(ssr[gp], Tcell[2 * gp + kk]));
+                        for (int gp = 0; gp < 4; ++gp)   // ssr[gp] = 0 for gp >= G
+                            ct = cadd(ct, cscale(ssr[gp], Tcell[(gp < G ? 2 * gp : 0) + kk]));
                         const cplx t = Tcell[li];
                         Tcell[R + li] = cscale(0.25 * dx, ct);
                         n0 = t.re;
