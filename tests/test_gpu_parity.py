@@ -63,6 +63,11 @@ def _cases():
         # (scattering ratio near one), delta = 0.23 at dt = 0.1 s
         "rosa_S8_dt10": (W.rosa(J=50, N=8, dt=10.0), 2),
         "rosa_S16_dt0.1": (W.rosa(J=200, N=16, dt=0.1), 2),
+        # 64 directions: a group spans the whole wave (the cross-lane sums
+        # pair lanes 32 apart), one pair per lane (G = 1) or two (G = 2)
+        "regions48_N64": (W.regions(seed=11, J=48, N=64, n_regions=6, length=2.0, dt=0.1), 2),
+        "multigroup16_N64_G2": (W.multigroup(seed=12, J=16, N=64, G=2, n_regions=4, length=0.5,
+                                             speeds=(20.0, 1.0), dt=0.05), 2),
     }
 
 
@@ -508,7 +513,8 @@ def test_structured_converges_to_oracle(name):
 
 
 @pytest.mark.parametrize("name", ["homogeneous64_n32", "regions512_n64", "multigroup192_n128",
-                                  "multigroup128_n256", "multigroup40_n512", "single_cell", "rosa_S16_dt0.1"])
+                                  "multigroup128_n256", "multigroup40_n512", "single_cell", "rosa_S16_dt0.1",
+                                  "regions48_N64", "multigroup16_N64_G2"])
 @pytest.mark.parametrize("max_wg", [None, "2"])
 def test_structured_staged_and_direct_bodies_agree(name, max_wg, monkeypatch):
     """The staged iteration body (tile inputs staged into LDS one tile ahead)
