@@ -136,19 +136,19 @@ __device__ inline void wait_memory() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 // thread waits for its own stores to complete, the workgroup meets, thread 0
 // publishes the workgroup's partial and arrives with relaxed atomics (the
 // release of the memory model minus the L2 writeback, which only non-coherent
-// data would need).  The workgroup whose arrival completes the count sums the
-// partials (ascending workgroup order through a fixed-shape reduction, so the
-// total does not depend on which workgroup does it), publishes the total and
-// raises the release word; the others wait for that word and read the one
-// total (the acquire minus the L2 invalidate, so the workgroups keep their
-// cached read-only data).  Round `round` (0, 1, ...) must grow by one per
-// call; partials and totals alternate between two rows.  Every wait is
-// bounded as in grid_sync_sum.
+// data would need).  The workgroup whose arrival completes the count raises
+// the release word at once; the others wait for it (the acquire minus the L2
+// invalidate, so the workgroups keep their cached read-only data).  Then every
+// workgroup sums the published partials itself, in ascending workgroup order
+// through the same fixed-shape reduction, so all hold the same total without
+// a round trip through a published total.  Round `round` (0, 1, ...) must grow
+// by one per call; the partials alternate between two rows (a row is
+// rewritten two rounds later, after every workgroup has read it).  Every wait
+// is bounded as in grid_sync_sum.
 template <int BS>
 __device__ inline bool grid_sync_coherent(const Slab &S, unsigned wg, unsigned nwg, int round, double wg_sum,
                                           int *s_flag, double *s_tmp, double *total) {
     double *part = S.partials + (size_t)(round & 1) * nwg;
-    double *tot_slot = S.partials + (size_t)2 * nwg + (round & 1);
     uint64_t *release = S.bar + kBarStride;
     const uint64_t target = (uint64_t)round + 1;
     wait_memory();
@@ -167,38 +167,32 @@ __device__ inline bool grid_sync_coherent(const Slab &S, unsigned wg, unsigned n
             const uint64_t ot = __hip_atomic_fetch_add(S.bar, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             last = ot + 1 == target * ngrp;
         }
-        s_flag[3] = last;
-    }
-    __syncthreads();
-    if (s_flag[3]) {
-        // every partial of this round is published: sum them, publish the total
-        double v = 0.0;
-        for (unsigned k = threadIdx.x; k < nwg; k += BS) v += ld_coherent(part + k);
-        v = block_sum_t<BS>(v, s_tmp);
-        if (threadIdx.x == 0) {
-            st_coherent(tot_slot, v);
-            wait_memory();
-            __hip_atomic_store(release, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_tmp[BS / 64] = v;
-            s_flag[2] = 0;
-        }
-    } else if (threadIdx.x == 0) {
         int bad = 0;
-        long spins = 0;
-        while (__hip_atomic_load(release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) {
-                __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                bad = 1;
-                break;
+        if (last) {
+            __hip_atomic_store(release, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long spins = 0;
+            while (__hip_atomic_load(release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kSpinLimit) {
+                    __hip_atomic_store(&S.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bad = 1;
+                    break;
+                }
             }
         }
-        s_tmp[BS / 64] = bad ? __builtin_nan("") : ld_coherent(tot_slot);
         s_flag[2] = bad;
     }
     __syncthreads();
+    const int bad = s_flag[2];
+    double v = 0.0;
+    if (!bad)
+        for (unsigned k = threadIdx.x; k < nwg; k += BS) v += ld_coherent(part + k);
+    v = block_sum_t<BS>(v, s_tmp);
+    if (threadIdx.x == 0) s_tmp[BS / 64] = bad ? __builtin_nan("") : v;
+    __syncthreads();
     *total = s_tmp[BS / 64];
-    return s_flag[2] == 0;
+    return bad == 0;
 }
 
 // Orders the LDS accesses of one wave before and after it (the wave's LDS
