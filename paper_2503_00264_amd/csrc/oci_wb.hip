@@ -31,10 +31,10 @@
 // The result is the exact OCI iterate (eq. oci) up to rounding, so a step
 // stops where the dense solve stops.  Per iteration a thread owns Q of a
 // cell's (g, m) pairs; a cell's lanes lie in one wave, so the moments and the
-// capacitance products need only wave-local LDS.  Incident edges are read
-// from the previous iterate in global memory (only the two outgoing corners
-// of each (g, m) are written per iteration), and one grid barrier per
-// iteration carries the norm (grid_sync_sum), as in the dense global kernel.
+// capacitance products need only the wave (cross-lane sums, wave-local LDS).
+// Incident edges are read from the previous iterate in global memory (only
+// the two outgoing corners of each (g, m) are written per iteration), and one
+// grid barrier per iteration carries the norm (grid_sync_coherent).
 // When the stopping rule holds after iteration l, the workgroups recompute
 // iteration l once more from the same inputs (identical arithmetic) and write
 // the whole final iterate.
@@ -489,9 +489,11 @@ __device__ __attribute__((always_inline)) inline void wb_body(const Slab &S, con
 //   waits for the staged data of t: the rows of (I - W C)^-1 of its cells,
 //   then psi_{k-1/2}, upstream corners, the cells' sources, scalar flux,
 //   cross sections and widths;
-//   forms b and z = L_c^-1 b; then issues the staging of t + 1 (the rows into
-//   the other of two row buffers, then the inputs);
-//   sums the moments over m by a butterfly across the N lanes of each group;
+//   reads all of it from LDS before using any, and the incident flux at the
+//   slab's ends; then issues the staging of t + 1 (the rows into the other of
+//   two row buffers, then the inputs);
+//   forms b and z = L_c^-1 b and sums the moments over m across the N lanes
+//   of each group (DPP and permlane exchanges, no LDS);
 //   forms t = (I - W C)^-1 V^T z and C t = (dx/4) (Sigma_s (x) I) t; stores
 //   the new scalar flux;
 //   forms x = z + L_c^-1 (C t)_g and stores the outgoing corners.
