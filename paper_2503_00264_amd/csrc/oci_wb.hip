@@ -614,8 +614,11 @@ __device__ inline cplx row_dot_r(const cplx *row, const cplx *v) {
 // Cross-lane sums without LDS.  Lane partners across bit B of the lane index:
 // B = 5 and 4 by the permlane swaps (lanes i and i ^ 32, i and i ^ 16), B = 3
 // and 2 by the DPP row mirrors (i and i ^ 15, i and i ^ 7 within rows of 16
-// lanes), B = 1 and 0 by DPP quad permutations (i ^ 2, i ^ 1).  Every lane of
-// the wave takes part.
+// lanes), B = 1 and 0 by DPP quad permutations (i ^ 2, i ^ 1).  The mirrors
+// flip lower bits as well, but taken from the highest bit down the flips (32,
+// 16, 15, 7, 2, 1) are independent, so each level adds two disjoint partial
+// sums and a lane ends with the sum over its whole group.  Every lane of the
+// wave takes part.
 template <int B>
 struct LaneXor {
     static constexpr int kDpp = B == 3 ? 0x140 : B == 2 ? 0x141 : B == 1 ? 0x4E : 0xB1;
