@@ -459,12 +459,32 @@ def sequential(probs, K, tol, torch, B, method, precision):
                 iterations_per_step_max=int(its.max()), iterations_per_step_mean=round(float(its.mean()), 2))
 
 
+def wb_staged_shape(J, N, G):
+    """The library's shape rule for the staged structured body: N a power of
+    two in 8..64, G in {1, 2, 4}, at most two (g, m) pairs per lane, a wave's
+    rows of (I - W C)^-1 within 2 KiB and its per-cell data within 1 KiB,
+    32-bit byte offsets.  A batch runs the staged body when every slab has
+    such a shape."""
+    if N < 8 or N > 64 or N & (N - 1) or G not in (1, 2, 4) or N * G > 128:
+        return False
+    lc = 1
+    while lc < N * G:
+        lc <<= 1
+    cpw = 64 // min(lc, 64)
+    return cpw * 4 * G * G <= 128 and cpw * G <= 8 and J * N * G * 32 < 2 ** 31
+
+
 def batch_structured_bytes(probs):
     """Algorithmic bytes per cell-iteration of the structured solve, FP64
     words: psi_{k-1/2} (2NG), the incident and the outgoing corners (2NG
-    each), the source (4G), the scalar flux read and written (4G each) and the
-    cell's capacitance rows (2 x (2G)^2 complex words)."""
-    return np.array([8 * (6 * p["N"] * p["G"] + 12 * p["G"]) + 16 * 8 * p["G"] ** 2
+    each), the source (4G), the scalar flux read and written (4G each), the
+    cell's cross sections and width (G^2 + G + 1), and its capacitance rows:
+    the (2G)^2 complex words of (I - W C)^-1 for the staged body (which forms
+    C t from Sigma_s), twice that for the direct body (which also reads the
+    rows of C (I - W C)^-1)."""
+    staged = all(wb_staged_shape(p["J"], p["N"], p["G"]) for p in probs)
+    rows = 64 if staged else 128   # bytes per G^2
+    return np.array([8 * (6 * p["N"] * p["G"] + 12 * p["G"] + p["G"] ** 2 + p["G"] + 1) + rows * p["G"] ** 2
                      for p in probs], dtype=np.float64)
 
 
@@ -503,10 +523,10 @@ def batch_main(a, torch, B):
                              STRUCTURED_SOURCES)
     roof["traffic"] = None if ratio is None else round(ratio * roof["bytes_per_step"], 1)
     roof["note"] = ("algorithmic bytes of the structured solve per cell-iteration (psi_{k-1/2}, incident "
-                    "and outgoing corners, source, scalar flux, capacitance rows) times each slab's "
-                    "cell-iterations, over the replayed graph's time per step (the per-step bookkeeping "
-                    "kernels included); traffic = the committed counters' HBM bytes per algorithmic byte "
-                    "times this run's algorithmic bytes")
+                    "and outgoing corners, source, scalar flux read and written, cross sections and width, "
+                    "the rows of (I - W C)^-1 the staged body reads) times each slab's cell-iterations, over "
+                    "the replayed graph's time per step (the per-step bookkeeping kernels included); traffic = "
+                    "the committed counters' HBM bytes per algorithmic byte times this run's algorithmic bytes")
     out = {
         "metric": "cell-solves/s and s per converged step: FP32-refined vs FP64 OCI vs SI @1e-10",
         "value": round(head["cell_solves_per_s"], 1), "unit": "cell-solves/s", "n_gpus": 1, "steps": K,
