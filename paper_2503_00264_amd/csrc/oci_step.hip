@@ -568,9 +568,12 @@ constexpr int kDppHalfMirror = 0x141;  // lane i <- 7 - i within 8
 constexpr int kDppMirror = 0x140;      // lane i <- 15 - i within 16
 constexpr int kDppRor4 = 0x124;        // rotate the row by 4 lanes
 constexpr int kDppRor8 = 0x128;        // rotate the row by 8 lanes
+// Every lane reads a lane of its own row, so no lane keeps an old value: a lane
+// whose source is disabled reads zero (bound_ctrl), and the destination needs
+// no initialisation.
 template <int CTRL>
 __device__ inline int dpp_i32(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ inline double dpp_f64(double v) {
@@ -583,15 +586,47 @@ __device__ inline double readlane_f64(double v, int lane) {
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
     return __hiloint2double(hi, lo);
 }
-// Sum over the 64 lanes of the wave in a fixed order; every lane gets the
-// same value (each butterfly step adds two equal-order partial sums, and
-// floating-point addition is commutative).
+// Across rows: lanes i and i ^ 16 (B = 4) or i and i ^ 32 (B = 5) exchange
+// their values by a permlane swap (one instruction per dword, no LDS).  The
+// swap of (v, v) leaves the lower-half lanes their own value in the first
+// result and the partner's in the second, the upper-half lanes the reverse;
+// either way a lane holds both values.
+template <int B>
+__device__ inline double xor_add_f64(double v) {
+    static_assert(B == 4 || B == 5, "row pairs or wave halves");
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    unsigned l0, l1, h0, h1;
+    if constexpr (B == 5) {
+        const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        l0 = a[0]; l1 = a[1]; h0 = b[0]; h1 = b[1];
+    } else {
+        const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        l0 = a[0]; l1 = a[1]; h0 = b[0]; h1 = b[1];
+    }
+    return __hiloint2double((int)h0, (int)l0) + __hiloint2double((int)h1, (int)l1);
+}
+template <int B>
+__device__ inline int xor_max_i32(int v) {
+    static_assert(B == 4 || B == 5, "row pairs or wave halves");
+    if constexpr (B == 5) {
+        const auto a = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+        return max((int)a[0], (int)a[1]);
+    } else {
+        const auto a = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+        return max((int)a[0], (int)a[1]);
+    }
+}
+// Sum over the 64 lanes of the wave in a fixed order, (r0 + r1) + (r2 + r3)
+// over the four row sums; every lane gets the same value (each step adds two
+// equal-order partial sums, and floating-point addition is commutative).
 __device__ inline double wave_sum_dpp(double v) {
     v += dpp_f64<kDppXor1>(v);
     v += dpp_f64<kDppXor2>(v);
     v += dpp_f64<kDppHalfMirror>(v);
     v += dpp_f64<kDppMirror>(v);
-    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+    return xor_add_f64<5>(xor_add_f64<4>(v));
 }
 // Maximum over aligned groups of TPC lanes (TPC = 8 .. 64).
 template <int TPC>
@@ -600,10 +635,8 @@ __device__ inline int seg_max_i32(int v) {
     v = max(v, dpp_i32<kDppXor2>(v));
     v = max(v, dpp_i32<kDppHalfMirror>(v));
     if constexpr (TPC >= 16) v = max(v, dpp_i32<kDppMirror>(v));
-    if constexpr (TPC == 32) v = max(v, __shfl_xor(v, 16, 64));
-    if constexpr (TPC == 64)
-        v = max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-                max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+    if constexpr (TPC >= 32) v = xor_max_i32<4>(v);
+    if constexpr (TPC == 64) v = xor_max_i32<5>(v);
     return v;
 }
 
@@ -934,6 +967,8 @@ void k_oci_local(Slab S, StepIO io, int ntiles) {
                     wx += dpp_f64<kDppRor8>(wx);
                     off = 16;
                 }
+                if (off == 16 && N >= 8) { wx = xor_add_f64<4>(wx); off = 32; }
+                if (off == 32 && N >= 16) { wx = xor_add_f64<5>(wx); off = 64; }
                 for (; off <= 2 * N; off <<= 1) wx += __shfl_xor(wx, off, 64);
                 if (live && t < n && (t >> 2) % N == 0) {
                     const int fi = (t / (4 * N)) * 4 + (t & 3);
@@ -1310,6 +1345,8 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
                 wx += dpp_f64<kDppRor8>(wx);
                 off = 16;
             }
+            if (off == 16 && N >= 8) { wx = xor_add_f64<4>(wx); off = 32; }
+            if (off == 32 && N >= 16) { wx = xor_add_f64<5>(wx); off = 64; }
             for (; off <= 2 * N; off <<= 1) wx += __shfl_xor(wx, off, 64);
             if (ri & res::PHI) {
                 const int fi = g * 4 + u;
