@@ -1250,10 +1250,13 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
         const int cl = tq >> LOGT, t = tq & (TPC - 1);
         const int m = ri & 0xFF, g = (ri >> 8) & 0xFF, u = (ri >> 16) & 3;
         const unsigned cb = (unsigned)l % NCOPY, nb = ((unsigned)l + 1) % NCOPY;
-        const double *Lp = L_psi0 + ((size_t)cb * CPT + cl) * n;   // this cell's Psi^(l)
-        const double *Lf = L_phi0 + ((size_t)cb * CPT + cl) * 4 * G;
-        double *Np = L_psi0 + ((size_t)nb * CPT + cl) * n;         // ... and Psi^(l+1)
-        double *Nf = L_phi0 + ((size_t)nb * CPT + cl) * 4 * G;
+        // per-lane offsets by 24-bit multiplies (full rate; cl < CPT, n and 4G
+        // at most NP), the copy's base in scalar registers
+        const unsigned cln = __umul24((unsigned)cl, (unsigned)n), clf = __umul24((unsigned)cl, 4u * G);
+        const double *Lp = L_psi0 + (size_t)cb * CPT * n + cln;      // this cell's Psi^(l)
+        const double *Lf = L_phi0 + (size_t)cb * CPT * 4 * G + clf;
+        double *Np = L_psi0 + (size_t)nb * CPT * n + cln;            // ... and Psi^(l+1)
+        double *Nf = L_phi0 + (size_t)nb * CPT * 4 * G + clf;
         const int lp = l - LAG;                                   // iteration whose partials this one adds
         const bool lpv = lp >= l0;                                // ... one of this step
         const uint64_t *part_prev = part_bits + (size_t)(lp & (kPartSlots - 1)) * nwg;
@@ -1262,7 +1265,7 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
         // this wave's share of the partials of iteration lp, loaded now and
         // added before the barrier
         const int sh = (tq >> 6) - WS0;
-        const int q0 = sh * Sw + (tq & 63);
+        const int q0 = __mul24(sh, Sw) + (tq & 63);   // |sh| <= W, Sw <= the grid size
         const bool qon = lpv && sh >= 0 && sh < WSN && (tq & 63) < Sw && q0 < (int)nwg;
         const uint64_t qv = qon ? ld_bits(part_prev + q0) : kSlotEmpty;
 
@@ -1302,7 +1305,8 @@ void k_oci_res(Slab S, StepIO io, int ntiles) {
                 const double2 pa = *reinterpret_cast<const double2 *>(Lp + (t & ~3));
                 const double2 pc = *reinterpret_cast<const double2 *>(Lp + (t & ~3) + 2);
                 double sc = 0.0;
-                for (int gp = 0; gp < G; ++gp) sc += s_scat[cl][g * G + gp] * Lf[gp * 4 + u];
+                const double *sg = &s_scat[cl][__umul24((unsigned)g, (unsigned)G)];
+                for (int gp = 0; gp < G; ++gp) sc += sg[gp] * Lf[gp * 4 + u];
                 r = b - (ca.x * pa.x + ca.y * pa.y + cc.x * pc.x + cc.y * pc.y) + sc;
             }
             int ex = (int)(((uint64_t)__double_as_longlong(r) >> 52) & 0x7FF);
