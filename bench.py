@@ -665,7 +665,7 @@ def main():
         cpu_child(a.cpu_child)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only (one slab batch per device); --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
     from paper_2503_00264_amd import binding as B
